@@ -1,0 +1,210 @@
+/*
+ * hermite.h -- C ABI of the MI355X (gfx950) modified Hermite N-body hot path.
+ *
+ * Method: A. J. Dittmann, "Modified Hermite Integrators of Arbitrary Order"
+ * (MNRAS 2020, arXiv:2006.02501).  An order-2(p+1) scheme (p = 1, 2, 3 for
+ * 4th, 6th, 8th order; Sec. 2, after Eq. 8) evaluates the softened pair
+ * acceleration a_ij = G m_j r_ij (r_ij^2 + eps^2)^(-3/2) (Sec. 3, opening
+ * paragraph) and its first p time derivatives by direct O(N^2) summation,
+ * once per predict-evaluate-correct iteration of a P(EC)^n step (Sec. 2.1,
+ * end); between evaluations it runs a Taylor predictor and the modified
+ * corrector of Eq. 22-24 (velocity first, then position; Eq. 6-8).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All particle arrays are DEVICE pointers to FP64 data owned by the caller
+ *   (e.g. torch tensors), laid out structure-of-arrays: a "[3][n] block" is
+ *   x-components of all n particles, then y, then z.  "[k][3][n]" is k such
+ *   blocks back to back.  The library never frees or reallocates them.
+ * - The library owns only its workspace (split partial sums, batched-plan
+ *   tables, the captured graph), allocated in *_create and freed in
+ *   hermite_destroy.
+ * - Every call is asynchronous on the HIP stream given to *_create (NULL =
+ *   the null stream).  Only hermite_last_error and the optional finite-value
+ *   check synchronise.
+ * - Arguments are validated on the host before any HIP call; a bad argument
+ *   returns an error code and enqueues nothing.  Nothing is thrown across the
+ *   ABI.  After an error, hermite_last_error(ctx) gives a message.
+ * - One context is used by one host thread at a time.
+ * - Results are bitwise reproducible for a given context configuration and
+ *   n: the sums use a fixed order and no atomics.
+ * - Negative dt integrates backwards with the same formulas.
+ */
+#ifndef HERMITE_H
+#define HERMITE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hermite_ctx hermite_ctx;
+
+typedef enum {
+    HERMITE_OK = 0,
+    HERMITE_E_ARG = -1,        /* bad pointer, size, dt, n_iter, eps2, ...          */
+    HERMITE_E_ORDER = -2,      /* order not in {4, 6, 8}                           */
+    HERMITE_E_ALLOC = -3,      /* device allocation failed / workspace too small   */
+    HERMITE_E_HIP = -4,        /* a HIP runtime call failed (message kept)         */
+    HERMITE_E_NONFINITE = -5,  /* finite check enabled and a result is inf / NaN   */
+    HERMITE_E_STATE = -6       /* called before hermite_init on this state         */
+} hermite_status;
+
+typedef enum {
+    HERMITE_FP64 = 0,   /* every operation in FP64                                   */
+    HERMITE_MIXED = 1   /* FP64 state and pairwise differences; the r^-3 pair term
+                           and its derivative chain in FP32, summed in FP32 within
+                           a j-tile and in FP64 across tiles (the paper suggests
+                           lower precision for the higher-order terms on
+                           accelerators, Sec. 4)                                   */
+} hermite_precision;
+
+typedef enum {
+    HERMITE_CORR_MODIFIED = 0,  /* beta_opt of Eq. 21: Eq. 22 / 23 / 24 (default)     */
+    HERMITE_CORR_BETA1 = 1,     /* beta = 1: the position formula exact one order
+                                   higher (the standard time-symmetric corrector at
+                                   4th order, Sec. 3.1)                               */
+    HERMITE_CORR_SHIFTED = 2    /* beta = 2 - beta_opt: drops the F_{2p+2} term's
+                                   endpoint derivative (the unmodified 6th/8th-order
+                                   correctors the paper compares against)            */
+} hermite_corrector;
+
+typedef struct {
+    int32_t order;         /* 4, 6 or 8 (= 2(p+1))                                  */
+    int32_t precision;     /* hermite_precision                                     */
+    int32_t corrector;     /* hermite_corrector                                     */
+    int32_t check_finite;  /* nonzero: hermite_step / hermite_batch_run check every
+                              output for inf / NaN (synchronises; E_NONFINITE)     */
+    double G;              /* gravitational constant                                */
+    double eps2;           /* softening eps^2 >= 0 (Sec. 3: eps = 1e-8 or 1e-6)     */
+} hermite_params;
+
+/*
+ * Particle state, p = order/2 - 1.  All pointers are device pointers, FP64,
+ * caller-owned, SoA as described above.
+ *   mass   [n]
+ *   pos    [3][n]        x at time t
+ *   vel    [3][n]        v at time t
+ *   deriv  [2p][3][n]    a^(0..2p-1) at time t (a, adot, a^(2), ..., written by
+ *                        hermite_init, advanced by the last correction of a step)
+ *   pred   [p+1][3][n]   the path of the current iterate: x, v and, for p >= 2,
+ *                        a (and adot for p = 3) -- what the evaluation reads
+ *   eval   [p+1][3][n]   a^(0..p) from the latest evaluation
+ * t is a host scalar advanced by the last correction of each step.
+ * initialized is set to 1 by hermite_init (a caller restoring a saved state
+ * sets it itself: (t, mass, pos, vel, deriv) is the complete state).
+ */
+typedef struct {
+    int64_t n;
+    const double *mass;
+    double *pos;
+    double *vel;
+    double *deriv;
+    double *pred;
+    double *eval;
+    double t;
+    int32_t initialized;
+    int32_t reserved;
+} hermite_state;
+
+/* Create a context for states of up to n_max particles (n_max >= 0).
+ * hip_stream is a hipStream_t (NULL = null stream).  Validates *prm:
+ * order -> E_ORDER; precision/corrector out of range, G not finite,
+ * eps2 < 0 or not finite, n_max < 0, out NULL -> E_ARG.  Allocates the
+ * split-sum workspace for n_max (E_ALLOC on failure). */
+hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hip_stream,
+                              hermite_ctx **out);
+
+/* Free the workspace and the context (NULL is accepted). */
+hermite_status hermite_destroy(hermite_ctx *ctx);
+
+/* Change the stream later calls are enqueued on. */
+hermite_status hermite_set_stream(hermite_ctx *ctx, void *hip_stream);
+
+/* Explicit initial derivatives (Sec. 3, second paragraph): a^(0..2p-1) at t
+ * from pos and vel by passes of the generic-order pair derivative
+ * (a, adot from x, v; then a^(2), a^(3); then, at 8th order, a^(4), a^(5)),
+ * always in FP64.  Writes s->deriv (uses s->eval and s->pred as scratch),
+ * sets s->initialized.  E_ARG on NULL pointers or n > n_max. */
+hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s);
+
+/* Taylor predictor (Sec. 3, second paragraph) with every stored derivative:
+ * x to dt^(2p+1), v to dt^(2p), a to dt^(2p-1), adot to dt^(2p-2).
+ * Writes s->pred.  E_ARG if dt is 0 or not finite; E_STATE before init. */
+hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt);
+
+/* One evaluation (the O(N^2) hot loop): for every i,
+ *   a^(k)_i = sum_{j != i} d^k/dt^k [ G m_j r_ij (r_ij^2 + eps^2)^(-3/2) ],
+ * k = 0..p, along the path s->pred (x, v, a, adot of every particle).
+ * Self terms are excluded by index.  Writes s->eval. */
+hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s);
+
+/* Modified corrector (Eq. 6-8; Eq. 22-24 for the default corrector) from
+ * the start-of-step state (pos, vel, deriv[0..p]) and s->eval:
+ *   v1 = v0 + sum_{k=0..p}   cv_k (a1^(k) +- a0^(k)) dt^(k+1)
+ *   x1 = x0 + sum_{k=0..p+1} cx_k (q1^(k) +- q0^(k)) dt^(k+1),  q = (v, a, adot, ...)
+ * (+ for even k, - for odd k).  last_iter == 0: writes the next iterate into
+ * s->pred (x1, v1 and the evaluated a, adot as the relative-acceleration path).
+ * last_iter != 0: overwrites pos, vel with x1, v1, sets deriv[0..p] = eval
+ * and deriv[p+1..2p-1] to the Hermite interpolant's derivatives at the end of
+ * the step, and advances s->t by dt. */
+hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter);
+
+/* One P(EC)^n step: predict, then n_iter times (force_derivs, correct),
+ * the last correction with last_iter = 1.  E_ARG if n_iter < 1. */
+hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32_t n_iter);
+
+/* Energy diagnostic (Sec. 3.1): phi[i] = -sum_{j != i} G m_j (r_ij^2+eps^2)^(-1/2)
+ * at s->pos, FP64, written to the device array phi[n]. */
+hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, double *phi);
+
+/*
+ * Batched form: n_sys independent systems concatenated in one state
+ * (particles offsets[s] .. offsets[s+1]-1 belong to system s; offsets is a
+ * HOST array of n_sys+1 nondecreasing values starting at 0, each system of
+ * 1..64 particles).  Pair sums run only inside a system.  All steps of all
+ * systems run in one persistent kernel launch, replayed from a captured HIP
+ * graph; systems are packed into 64-lane wavefronts and handed out longest
+ * first from a device work counter.
+ */
+hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
+                                    void *hip_stream, hermite_ctx **out);
+
+/* Explicit initial derivatives of every system (FP64), as hermite_init. */
+hermite_status hermite_batch_init(hermite_ctx *ctx, hermite_state *s);
+
+/* n_steps P(EC)^n steps of every system; dt_sys is a DEVICE array [n_sys] of
+ * per-system steps.  Updates pos, vel, deriv in place (pred and eval are not
+ * used).  s->t is advanced by n_steps (per-system times are n_steps*dt_sys). */
+hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys,
+                                 int32_t n_steps, int32_t n_iter);
+
+/*
+ * Launch-shape tuning for hermite_force_derivs.
+ *   i_per_thread   1 or 2 i-particles per lane
+ *   j_split        number of j-ranges summed by separate workgroups (0 = auto,
+ *                  1..64; an upper bound: it is reduced to what the workspace
+ *                  holds and to one range per 256 j)
+ *   j_source       0: j-particles staged through LDS tiles by each workgroup;
+ *                  1: j-particles packed once per evaluation into 128-byte
+ *                  records and streamed through the scalar unit into SGPRs
+ * E_ARG for values outside these sets.  hermite_autotune times the supported
+ * shapes on the given state (which must hold a valid path in s->pred),
+ * keeps the fastest and returns it through the non-NULL out pointers.
+ */
+hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source);
+hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_per_thread, int32_t *j_split,
+                                int32_t *j_source);
+
+/* Message of the last failed call on ctx ("" if none; static string for NULL). */
+const char *hermite_last_error(const hermite_ctx *ctx);
+
+/* Library version string. */
+const char *hermite_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERMITE_H */

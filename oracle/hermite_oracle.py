@@ -159,7 +159,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_pair_derivs.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int32, ctypes.c_double,
-                                           ctypes.c_double, ctypes.c_int64, ip, dp, dp]
+                                           ctypes.c_double, ctypes.c_int64, ip, dp, dp, dp]
         lib.oracle_pair_derivs.restype = ctypes.c_int
         lib.oracle_potential.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int64, ip, dp]
@@ -182,12 +182,16 @@ class NonFiniteError(FloatingPointError):
     pass
 
 
-def pair_derivs(mass, path, K=None, G=1.0, eps2=0.0, i_list=None, with_mag=False):
+def pair_derivs(mass, path, K=None, G=1.0, eps2=0.0, i_list=None, with_mag=False, with_scale=False):
     """a^(0..K) on each target particle from the softened pair force.
 
     mass : [n];  path : sequence of K+1 arrays [3][n] = x^(0..K) (x, v, a, ...)
-    Returns out [K+1][3][n_i] (and mag [K+1][n_i], the sum over j of the
-    Euclidean norm of each pair term, if ``with_mag``).
+    Returns out [K+1][3][n_i]; with ``with_mag`` also mag [K+1][n_i], the sum
+    over j of the Euclidean norm of each pair term; with ``with_scale`` also
+    nat [K+1][n_i], the sum over j of each pair's natural k-th derivative
+    scale G m_j s^-2 omega^k (s the softened distance, omega the fastest rate
+    (|x^(k)_j - x^(k)_i| / s)^(1/k) of the relative path): the size of the
+    change a relative rounding of the path inputs makes in a^(k).
     """
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     n = mass.shape[0]
@@ -202,13 +206,20 @@ def pair_derivs(mass, path, K=None, G=1.0, eps2=0.0, i_list=None, with_mag=False
         n_i, ip = il.shape[0], il.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     out = np.zeros((K + 1, 3, n_i))
     mag = np.zeros((K + 1, n_i)) if with_mag else None
+    nat = np.zeros((K + 1, n_i)) if with_scale else None
     rc = _load().oracle_pair_derivs(n, _dptr(mass), _dptr(P), K, float(G), float(eps2), n_i, ip,
-                                    _dptr(out), _dptr(mag) if with_mag else None)
+                                    _dptr(out), _dptr(mag) if with_mag else None,
+                                    _dptr(nat) if with_scale else None)
     if rc == -2:
         raise NonFiniteError("non-finite pair derivative (coincident particles with eps = 0?)")
     if rc != 0:
         raise ValueError("oracle_pair_derivs: bad arguments (%d)" % rc)
-    return (out, mag) if with_mag else out
+    res = (out,)
+    if with_mag:
+        res += (mag,)
+    if with_scale:
+        res += (nat,)
+    return res if len(res) > 1 else out
 
 
 def potential_per_particle(mass, x, G=1.0, eps2=0.0, i_list=None):

@@ -51,11 +51,16 @@ static double binom(int n, int k)
  * n_i      number of target particles; i_list[n_i] their indices (NULL = all, n_i = n)
  * out      [(K+1)][3][n_i] result a^(k)_c for each target
  * mag      [(K+1)][n_i]    sum over j of |a_ij^(k)| (Euclidean), may be NULL
+ * nat      [(K+1)][n_i]    sum over j of the pair's natural k-th derivative scale
+ *                          G m_j s^-2 omega^k, s = sqrt(r.r + eps^2), omega the
+ *                          fastest rate of the relative path, max_k (|r^(k)|/s)^(1/k):
+ *                          the size of the change that a relative rounding of
+ *                          r, v, a, ... produces in a^(k).  May be NULL.
  * returns 0 on success, -1 on bad arguments, -2 if any output is not finite
  */
 int oracle_pair_derivs(int64_t n, const double *mass, const double *path, int32_t K,
                        double G, double eps2, int64_t n_i, const int64_t *i_list,
-                       double *out, double *mag)
+                       double *out, double *mag, double *nat)
 {
     if (n < 0 || K < 0 || K > ORACLE_KMAX || eps2 < 0.0 || !mass || !path || !out) return -1;
     if (!i_list) n_i = n;
@@ -70,8 +75,8 @@ int oracle_pair_derivs(int64_t n, const double *mass, const double *path, int32_
         const int64_t i = i_list ? i_list[ii] : ii;
         if (i < 0 || i >= n) { bad |= 1; continue; }
         double acc[ORACLE_KMAX + 1][3];
-        double accm[ORACLE_KMAX + 1];
-        for (int k = 0; k <= K; ++k) { acc[k][0] = acc[k][1] = acc[k][2] = 0.0; accm[k] = 0.0; }
+        double accm[ORACLE_KMAX + 1], accn[ORACLE_KMAX + 1];
+        for (int k = 0; k <= K; ++k) { acc[k][0] = acc[k][1] = acc[k][2] = 0.0; accm[k] = 0.0; accn[k] = 0.0; }
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             double r[ORACLE_KMAX + 1][3];
@@ -105,6 +110,22 @@ int oracle_pair_derivs(int64_t n, const double *mass, const double *path, int32_
                 }
                 accm[m] += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
             }
+            if (nat) {
+                /* natural derivative scale of this pair: G m_j s^-2 omega^k with
+                   s = sqrt(r.r + eps^2), omega = max_k (|r^(k)| / s)^(1/k) */
+                const double sft = sqrt(w[0]);
+                double om = 0.0;
+                for (int k = 1; k <= K; ++k) {
+                    const double q = sqrt(r[k][0] * r[k][0] + r[k][1] * r[k][1] + r[k][2] * r[k][2]) / sft;
+                    const double rate = pow(q, 1.0 / (double)k);
+                    if (rate > om) om = rate;
+                }
+                double sc = fabs(gm) / w[0];
+                for (int m = 0; m <= K; ++m) {
+                    accn[m] += sc;
+                    sc *= om;
+                }
+            }
         }
         for (int k = 0; k <= K; ++k) {
             for (int c = 0; c < 3; ++c) {
@@ -112,6 +133,7 @@ int oracle_pair_derivs(int64_t n, const double *mass, const double *path, int32_
                 if (!isfinite(acc[k][c])) bad |= 2;
             }
             if (mag) mag[(int64_t)k * n_i + ii] = accm[k];
+            if (nat) nat[(int64_t)k * n_i + ii] = accn[k];
         }
     }
     if (bad & 1) return -1;

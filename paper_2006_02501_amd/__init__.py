@@ -1,0 +1,6 @@
+"""MI355X (gfx950) hot path of the modified Hermite integrators of
+Dittmann (2020, arXiv:2006.02501): HIP kernels behind a C ABI
+(``include/hermite.h``) and a thin ctypes binding."""
+from .hermite import (  # noqa: F401
+    BatchHermite, DeviceState, Hermite, HermiteError, load_library, version, CORRECTORS, PRECISIONS,
+)

@@ -1,0 +1,497 @@
+// O(N^2) evaluation of the softened pair acceleration and its time
+// derivatives (the hot loop of every P(EC)^n iteration).
+//
+// Layout on the chip: a workgroup is 4 wave64 (256 lanes).  Each lane keeps
+// IPT i-particles (their path x, v, a, adot and the running sums) in VGPRs.
+// The workgroup walks its j-range in tiles of 256 j-particles; every tile is
+// read from HBM once, coalesced (consecutive lanes, consecutive j), into LDS
+// as one row per j (G m, then the path components), and every lane then
+// reads the rows as wave-wide broadcasts.  The j-range is split over
+// gridDim.y workgroups so that a modest N still fills 256 CUs; the split
+// partial sums are added in a fixed order by a second kernel (no atomics,
+// bitwise reproducible).
+//
+// Chains: FP64 (everything double); Mixed (differences of the FP64 path in
+// double, then cast; the r^-3 term and its derivative chain in float,
+// summed in float over 32 j at a time and in double across those partial
+// sums); Generic (the FP64 recurrence up to the 5th derivative, for the
+// initialisation).
+#include "kernels.h"
+#include "pair_chain.h"
+
+namespace hermite {
+namespace {
+
+template <int K>
+struct Path {
+    const double *p[K + 1];
+};
+
+constexpr int kFold = 32;   // mixed chain: j-particles per FP32 partial sum
+
+template <int K>
+constexpr int row_stride() { return ((1 + 3 * (K + 1)) + 1) & ~1; }
+
+template <int K, Chain CH, int IPT, bool DIAG>
+__device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const float *__restrict__ mtile, int cnt,
+                                          int64_t j0, const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
+                                          double eps2, double (&acc)[IPT][K + 1][3], float (&accf)[IPT][K + 1][3])
+{
+    constexpr int RS = row_stride<K>();
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+        const double *row = tile + jj * RS;
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const bool self = DIAG && (j0 + jj == ii[q]);
+            if constexpr (CH == Chain::Fp64) {
+                double r[3], v[3], a[3], j[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = row[1 + c] - xi[q][0][c];
+                    v[c] = row[4 + c] - xi[q][1][c];
+                    if constexpr (K >= 2) a[c] = row[7 + c] - xi[q][2][c]; else a[c] = 0.0;
+                    if constexpr (K >= 3) j[c] = row[10 + c] - xi[q][3][c]; else j[c] = 0.0;
+                }
+                double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                double m = row[0];
+                if (DIAG) {
+                    w = self ? 1.0 : w;
+                    m = self ? 0.0 : m;
+                }
+                const double rinv = rsqrt64(w);
+                const double rinv2 = rinv * rinv;
+                const double mr3 = m * rinv * rinv2;
+                chain_accumulate<K, double>(r, v, a, j, mr3, rinv2, acc[q]);
+            } else if constexpr (CH == Chain::Mixed) {
+                float r[3], v[3], a[3], j[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = (float)(row[1 + c] - xi[q][0][c]);
+                    v[c] = (float)(row[4 + c] - xi[q][1][c]);
+                    if constexpr (K >= 2) a[c] = (float)(row[7 + c] - xi[q][2][c]); else a[c] = 0.0f;
+                    if constexpr (K >= 3) j[c] = (float)(row[10 + c] - xi[q][3][c]); else j[c] = 0.0f;
+                }
+                float w = __builtin_fmaf(r[0], r[0], __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], (float)eps2)));
+                float m = mtile[jj];
+                if (DIAG) {
+                    w = self ? 1.0f : w;
+                    m = self ? 0.0f : m;
+                }
+                const float rinv = rsqrt32(w);
+                const float rinv2 = rinv * rinv;
+                const float mr3 = m * rinv * rinv2;
+                chain_accumulate<K, float>(r, v, a, j, mr3, rinv2, accf[q]);
+            } else {
+                double r[K + 1][3];
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) r[k][c] = row[1 + 3 * k + c] - xi[q][k][c];
+                generic_accumulate<K>(r, eps2, row[0], self, acc[q]);
+            }
+        }
+    }
+}
+
+template <int K, Chain CH, int IPT>
+__global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
+                                                       double G, double eps2, int64_t j_chunk, int k_first,
+                                                       double *__restrict__ out)
+{
+    constexpr int RS = row_stride<K>();
+    __shared__ __align__(16) double tile[kTile * RS];
+    __shared__ float mtile[CH == Chain::Mixed ? kTile : 1];
+    const int tid = threadIdx.x;
+    const int64_t ib0 = (int64_t)blockIdx.x * (kBlock * IPT);
+    const int64_t ib1 = min(n, ib0 + (int64_t)(kBlock * IPT));
+    const int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
+    const int64_t jend = min(n, jbeg + j_chunk);
+
+    int64_t ii[IPT];
+    double xi[IPT][K + 1][3];
+    double acc[IPT][K + 1][3];
+    float accf[IPT][K + 1][3];
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        ii[q] = ib0 + q * kBlock + tid;
+        const bool ok = ii[q] < n;
+#pragma unroll
+        for (int k = 0; k <= K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xi[q][k][c] = ok ? path.p[k][c * n + ii[q]] : 0.0;
+                acc[q][k][c] = 0.0;
+                accf[q][k][c] = 0.0f;
+            }
+    }
+
+    for (int64_t j0 = jbeg; j0 < jend; j0 += kTile) {
+        const int cnt = (int)min((int64_t)kTile, jend - j0);
+        __syncthreads();
+        if (tid < cnt) {
+            const int64_t j = j0 + tid;
+            double *row = tile + tid * RS;
+            const double gm = G * mass[j];
+            row[0] = gm;
+            if constexpr (CH == Chain::Mixed) mtile[tid] = (float)gm;
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) row[1 + 3 * k + c] = path.p[k][c * n + j];
+        }
+        __syncthreads();
+        const bool diag = (j0 < ib1) && (ib0 < j0 + cnt);
+        if constexpr (CH != Chain::Mixed) {
+            if (diag)
+                tile_pass<K, CH, IPT, true>(tile, mtile, cnt, j0, ii, xi, eps2, acc, accf);
+            else
+                tile_pass<K, CH, IPT, false>(tile, mtile, cnt, j0, ii, xi, eps2, acc, accf);
+        } else {
+            // FP32 partial sums over kFold j at a time, folded into FP64: bounds
+            // the rounding that small terms suffer next to a dominant one.
+            for (int s0 = 0; s0 < cnt; s0 += kFold) {
+                const int cs = min(kFold, cnt - s0);
+                if (diag)
+                    tile_pass<K, CH, IPT, true>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+                else
+                    tile_pass<K, CH, IPT, false>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+#pragma unroll
+                for (int q = 0; q < IPT; ++q)
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            acc[q][k][c] += (double)accf[q][k][c];
+                            accf[q][k][c] = 0.0f;
+                        }
+            }
+        }
+    }
+
+    const int nv = K + 1 - k_first;
+    double *o = out + (int64_t)blockIdx.y * nv * 3 * n;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (ii[q] >= n) continue;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            if (k < k_first) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[((int64_t)(k - k_first) * 3 + c) * n + ii[q]] = acc[q][k][c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar-stream variant.  Every lane of a wave needs the same j-particle at the
+// same time, so the j-data is wave-uniform: it is packed once per evaluation
+// into 128-byte records and read with scalar loads into SGPRs, which the VALU
+// instructions take directly as operands.  No LDS, no barriers; the j-range
+// is walked in three parts so only the part that overlaps the workgroup's own
+// i-range pays for the self-term test.
+constexpr int kJRec = kJRecDoubles;   // packed j-record: G m, x, v, a, adot, float G m, pad
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void pack_j_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
+                                                        double G, double *__restrict__ jrec)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    double rec[kJRec];
+    const double gm = G * mass[j];
+    rec[0] = gm;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rec[1 + 3 * k + c] = k <= K ? path.p[k <= K ? k : 0][c * n + j] : 0.0;
+    rec[13] = __builtin_bit_cast(double, (uint64_t)__builtin_bit_cast(uint32_t, (float)gm));
+    rec[14] = 0.0;
+    rec[15] = 0.0;
+    double *dst = jrec + j * kJRec;
+#pragma unroll
+    for (int e = 0; e < kJRec; ++e) dst[e] = rec[e];
+}
+
+template <int K, Chain CH, int IPT, bool DIAG>
+__device__ __forceinline__ void stream_range(const double *__restrict__ jrec, int64_t jb, int64_t je,
+                                             const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
+                                             double eps2, double (&acc)[IPT][K + 1][3],
+                                             float (&accf)[IPT][K + 1][3])
+{
+    if (jb >= je) return;
+    constexpr int NJ = 1 + 3 * (K + 1);
+    // Software pipeline: the scalar loads of record j+1 are issued before the
+    // arithmetic of record j, so their latency hides behind it.
+    double nx[NJ];
+    uint64_t nxm;
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) nx[e] = jrec[jb * kJRec + e];
+    nxm = __builtin_bit_cast(uint64_t, jrec[jb * kJRec + 13]);
+    for (int64_t j = jb; j < je; ++j) {
+        double jd[NJ];
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) jd[e] = nx[e];
+        const float gmf = __builtin_bit_cast(float, (uint32_t)nxm);
+        const int64_t jn = (j + 1 < je) ? j + 1 : j;
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) nx[e] = jrec[jn * kJRec + e];
+        nxm = __builtin_bit_cast(uint64_t, jrec[jn * kJRec + 13]);
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const bool self = DIAG && (j == ii[q]);
+            if constexpr (CH == Chain::Fp64) {
+                double r[3], v[3], a[3], jk[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = jd[1 + c] - xi[q][0][c];
+                    v[c] = jd[4 + c] - xi[q][1][c];
+                    if constexpr (K >= 2) a[c] = jd[7 + c] - xi[q][2][c]; else a[c] = 0.0;
+                    if constexpr (K >= 3) jk[c] = jd[10 + c] - xi[q][3][c]; else jk[c] = 0.0;
+                }
+                double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                double m = jd[0];
+                if (DIAG) {
+                    w = self ? 1.0 : w;
+                    m = self ? 0.0 : m;
+                }
+                const double rinv = rsqrt64(w);
+                const double rinv2 = rinv * rinv;
+                chain_accumulate<K, double>(r, v, a, jk, m * rinv * rinv2, rinv2, acc[q]);
+            } else {
+                float r[3], v[3], a[3], jk[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = (float)(jd[1 + c] - xi[q][0][c]);
+                    v[c] = (float)(jd[4 + c] - xi[q][1][c]);
+                    if constexpr (K >= 2) a[c] = (float)(jd[7 + c] - xi[q][2][c]); else a[c] = 0.0f;
+                    if constexpr (K >= 3) jk[c] = (float)(jd[10 + c] - xi[q][3][c]); else jk[c] = 0.0f;
+                }
+                float w = __builtin_fmaf(r[0], r[0], __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], (float)eps2)));
+                float m = gmf;
+                if (DIAG) {
+                    w = self ? 1.0f : w;
+                    m = self ? 0.0f : m;
+                }
+                const float rinv = rsqrt32(w);
+                const float rinv2 = rinv * rinv;
+                chain_accumulate<K, float>(r, v, a, jk, m * rinv * rinv2, rinv2, accf[q]);
+            }
+        }
+    }
+}
+
+template <int K, Chain CH, int IPT, bool DIAG>
+__device__ __forceinline__ void stream_folded(const double *__restrict__ jrec, int64_t jb, int64_t je,
+                                              const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
+                                              double eps2, double (&acc)[IPT][K + 1][3],
+                                              float (&accf)[IPT][K + 1][3])
+{
+    if constexpr (CH != Chain::Mixed) {
+        stream_range<K, CH, IPT, DIAG>(jrec, jb, je, ii, xi, eps2, acc, accf);
+    } else {
+        for (int64_t s0 = jb; s0 < je; s0 += kFold) {
+            const int64_t s1 = min(je, s0 + (int64_t)kFold);
+            stream_range<K, CH, IPT, DIAG>(jrec, s0, s1, ii, xi, eps2, acc, accf);
+#pragma unroll
+            for (int q = 0; q < IPT; ++q)
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        acc[q][k][c] += (double)accf[q][k][c];
+                        accf[q][k][c] = 0.0f;
+                    }
+        }
+    }
+}
+
+template <int K, Chain CH, int IPT>
+__global__ __launch_bounds__(kBlock) void force_stream_kernel(int64_t n, const double *__restrict__ jrec,
+                                                              Path<K> path, double eps2, int64_t j_chunk,
+                                                              double *__restrict__ out)
+{
+    const int tid = threadIdx.x;
+    const int64_t ib0 = (int64_t)blockIdx.x * (kBlock * IPT);
+    const int64_t ib1 = min(n, ib0 + (int64_t)(kBlock * IPT));
+    const int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
+    const int64_t jend = min(n, jbeg + j_chunk);
+
+    int64_t ii[IPT];
+    double xi[IPT][K + 1][3];
+    double acc[IPT][K + 1][3];
+    float accf[IPT][K + 1][3];
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        ii[q] = ib0 + q * kBlock + tid;
+        const bool ok = ii[q] < n;
+#pragma unroll
+        for (int k = 0; k <= K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xi[q][k][c] = ok ? path.p[k][c * n + ii[q]] : 0.0;
+                acc[q][k][c] = 0.0;
+                accf[q][k][c] = 0.0f;
+            }
+    }
+    // [jbeg, d0) and [d1, jend) cannot contain one of this workgroup's i.
+    const int64_t d0 = max(jbeg, min(jend, ib0));
+    const int64_t d1 = max(d0, min(jend, ib1));
+    stream_folded<K, CH, IPT, false>(jrec, jbeg, d0, ii, xi, eps2, acc, accf);
+    stream_folded<K, CH, IPT, true>(jrec, d0, d1, ii, xi, eps2, acc, accf);
+    stream_folded<K, CH, IPT, false>(jrec, d1, jend, ii, xi, eps2, acc, accf);
+
+    double *o = out + (int64_t)blockIdx.y * (K + 1) * 3 * n;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (ii[q] >= n) continue;
+#pragma unroll
+        for (int k = 0; k <= K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[((int64_t)k * 3 + c) * n + ii[q]] = acc[q][k][c];
+    }
+}
+
+__global__ void reduce_splits_kernel(int64_t count, int nsplit, const double *__restrict__ partial,
+                                     double *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = partial[e];
+    for (int sp = 1; sp < nsplit; ++sp) s += partial[(int64_t)sp * count + e];
+    out[e] = s;
+}
+
+template <int K, Chain CH, int IPT>
+hipError_t launch_t(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+{
+    Path<K> path;
+    for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
+    const int64_t iblocks = (a.n + kBlock * IPT - 1) / (kBlock * IPT);
+    dim3 grid((unsigned)iblocks, (unsigned)nsplit);
+    hipLaunchKernelGGL((force_kernel<K, CH, IPT>), grid, dim3(kBlock), 0, st, a.n, a.mass, path, a.G, a.eps2,
+                       j_chunk, a.k_first, dst);
+    return hipGetLastError();
+}
+
+template <int K, Chain CH, int IPT>
+hipError_t launch_stream_t(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+{
+    Path<K> path;
+    for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
+    hipLaunchKernelGGL((pack_j_kernel<K>), dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a.n,
+                       a.mass, path, a.G, a.jrec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t iblocks = (a.n + kBlock * IPT - 1) / (kBlock * IPT);
+    dim3 grid((unsigned)iblocks, (unsigned)nsplit);
+    hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT>), grid, dim3(kBlock), 0, st, a.n, (const double *)a.jrec,
+                       path, a.eps2, j_chunk, dst);
+    return hipGetLastError();
+}
+
+template <Chain CH>
+hipError_t dispatch_stream(const ForceArgs &a, int ipt, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+{
+    if (ipt == 1) {
+        switch (a.K) {
+            case 1: return launch_stream_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
+            case 2: return launch_stream_t<2, CH, 1>(a, nsplit, j_chunk, dst, st);
+            case 3: return launch_stream_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (ipt == 2) {
+        switch (a.K) {
+            case 1: return launch_stream_t<1, CH, 2>(a, nsplit, j_chunk, dst, st);
+            case 2: return launch_stream_t<2, CH, 2>(a, nsplit, j_chunk, dst, st);
+            case 3: return launch_stream_t<3, CH, 2>(a, nsplit, j_chunk, dst, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <Chain CH>
+hipError_t dispatch(const ForceArgs &a, int ipt, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+{
+    if constexpr (CH == Chain::Generic) {
+        switch (a.K) {
+            case 1: return launch_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
+            case 3: return launch_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
+            case 5: return launch_t<5, CH, 1>(a, nsplit, j_chunk, dst, st);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (ipt == 1) {
+            switch (a.K) {
+                case 1: return launch_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
+                case 2: return launch_t<2, CH, 1>(a, nsplit, j_chunk, dst, st);
+                case 3: return launch_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        if (ipt == 2) {
+            switch (a.K) {
+                case 1: return launch_t<1, CH, 2>(a, nsplit, j_chunk, dst, st);
+                case 2: return launch_t<2, CH, 2>(a, nsplit, j_chunk, dst, st);
+                case 3: return launch_t<3, CH, 2>(a, nsplit, j_chunk, dst, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int auto_split(int64_t n, int ipt)
+{
+    if (n <= 0) return 1;
+    const int64_t iblocks = (n + kBlock * ipt - 1) / (kBlock * ipt);
+    const int64_t target = 1024;   // 4 workgroups (16 wave64) per CU on 256 CUs
+    int64_t s = (target + iblocks - 1) / iblocks;
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    if (s > tiles) s = tiles;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    return (int)s;
+}
+
+hipError_t launch_force(const ForceArgs &a, Chain chain, int ipt, int nsplit, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int nv = a.K + 1 - a.k_first;
+    if (nv <= 0 || a.K >= kMaxPath) return hipErrorInvalidValue;
+    const int64_t per_split = (int64_t)nv * 3 * a.n;
+    if (nsplit < 1) nsplit = 1;
+    if (nsplit > 1 && (int64_t)nsplit * per_split > a.partial_cap) {
+        nsplit = (int)(a.partial_cap / per_split);
+        if (nsplit < 2) nsplit = 1;
+    }
+    int64_t j_chunk = (a.n + nsplit - 1) / nsplit;
+    j_chunk = (j_chunk + kTile - 1) / kTile * kTile;
+    nsplit = (int)((a.n + j_chunk - 1) / j_chunk);
+    double *dst = nsplit > 1 ? a.partial : a.out;
+    const bool stream = a.jsource == JSource::Scalar && chain != Chain::Generic && a.k_first == 0 && a.jrec &&
+                        a.K <= 3;
+    hipError_t e;
+    switch (chain) {
+        case Chain::Fp64:
+            e = stream ? dispatch_stream<Chain::Fp64>(a, ipt, nsplit, j_chunk, dst, st)
+                       : dispatch<Chain::Fp64>(a, ipt, nsplit, j_chunk, dst, st);
+            break;
+        case Chain::Mixed:
+            e = stream ? dispatch_stream<Chain::Mixed>(a, ipt, nsplit, j_chunk, dst, st)
+                       : dispatch<Chain::Mixed>(a, ipt, nsplit, j_chunk, dst, st);
+            break;
+        default: e = dispatch<Chain::Generic>(a, ipt, nsplit, j_chunk, dst, st); break;
+    }
+    if (e != hipSuccess || nsplit == 1) return e;
+    const int64_t blocks = (per_split + 255) / 256;
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)blocks), dim3(256), 0, st, per_split, nsplit,
+                       (const double *)a.partial, a.out);
+    return hipGetLastError();
+}
+
+}  // namespace hermite

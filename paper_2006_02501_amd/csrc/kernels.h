@@ -1,0 +1,73 @@
+// Internal launcher declarations shared by the runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hermite {
+
+constexpr int kBlock = 256;   // threads per workgroup of the tiled evaluation (4 wave64)
+constexpr int kTile = 256;    // j-particles staged in LDS per tile
+constexpr int kMaxPath = 6;   // path derivatives x^(0..5) (generic initialisation)
+
+enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2 };
+
+// Where the evaluation reads the j-particles from: LDS tiles filled by the
+// workgroup, or packed records streamed through the scalar unit into SGPRs.
+enum class JSource { Lds = 0, Scalar = 1 };
+
+struct ForceArgs {
+    int64_t n;                    // particles (i and j range over all of them)
+    const double *mass;           // [n]
+    const double *path[kMaxPath]; // path[k] = [3][n] block of x^(k)
+    int K;                        // highest derivative evaluated
+    int k_first;                  // first derivative written (outputs k_first..K)
+    double G, eps2;
+    double *out;                  // [K+1-k_first][3][n]
+    double *partial;              // split partial sums [nsplit][K+1-k_first][3][n]
+    int64_t partial_cap;          // capacity of partial, in doubles
+    JSource jsource;              // j-particle source (Scalar needs jrec, K <= 3, k_first = 0)
+    double *jrec;                 // packed j-records [n][16] (Scalar source)
+};
+
+// Doubles per particle of the packed j-stream.
+constexpr int kJRecDoubles = 16;
+
+// Evaluates with the given chain, i-particles per lane and j-split count.
+hipError_t launch_force(const ForceArgs &a, Chain chain, int ipt, int nsplit, hipStream_t st);
+
+// j-split count the evaluation uses when the caller does not fix one.
+int auto_split(int64_t n, int ipt);
+
+hipError_t launch_predict(int p, int64_t n, double dt, const double *pos, const double *vel,
+                          const double *deriv, double *pred, hipStream_t st);
+
+hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, double *pos, double *vel,
+                          double *deriv, const double *eval, double *pred, hipStream_t st);
+
+hipError_t launch_potential(int64_t n, const double *mass, const double *pos, double G, double eps2,
+                            double *phi, hipStream_t st);
+
+// flag[0] is set to 1 if any of the count doubles is inf or NaN.
+hipError_t launch_check_finite(const double *data, int64_t count, int *flag, hipStream_t st);
+
+// Batched systems ------------------------------------------------------------
+struct BatchPlan {
+    int32_t n_sys;
+    int32_t n_bins;             // 64-lane wavefront bins
+    const int32_t *bin_start;   // [n_bins+1] index into bin_sys
+    const int32_t *bin_sys;     // systems, bin by bin
+    const int64_t *offsets;     // [n_sys+1] particle offsets
+    int *counter;               // work counter (device)
+};
+
+hipError_t launch_batch_init(const BatchPlan &plan, int p, int64_t n, const double *mass, const double *pos,
+                             const double *vel, double *deriv, double G, double eps2, hipStream_t st);
+
+hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int corrector, int64_t n,
+                            const double *mass, double *pos, double *vel, double *deriv, const double *dt_sys,
+                            int n_steps, int n_iter, double G, double eps2, int n_workgroups, hipStream_t st);
+
+hipError_t launch_reset_counter(int *counter, hipStream_t st);
+
+}  // namespace hermite

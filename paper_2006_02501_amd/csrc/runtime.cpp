@@ -1,0 +1,539 @@
+// Host runtime behind include/hermite.h: argument validation, workspace,
+// stream handling, launch-shape tuning, the P(EC)^n step sequence and the
+// captured graph of the batched form.
+#include "hermite.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using hermite::Chain;
+using hermite::ForceArgs;
+
+struct hermite_ctx {
+    hermite_params prm{};
+    int p = 1;
+    int64_t n_max = 0;
+    hipStream_t stream = nullptr;
+    double *partial = nullptr;
+    int64_t partial_cap = 0;
+    int *flag = nullptr;
+    int ipt = 1;
+    int nsplit = 0;          // 0: automatic
+    int jsource = 1;         // 0: LDS tiles, 1: scalar stream
+    double *jrec = nullptr;  // packed j-records [n_max][kJRecDoubles]
+    std::string err;
+    // batched form
+    bool batch = false;
+    int32_t n_sys = 0;
+    int32_t n_bins = 0;
+    int32_t max_size = 0;
+    std::vector<int64_t> offsets;
+    int32_t *d_bin_start = nullptr;
+    int32_t *d_bin_sys = nullptr;
+    int64_t *d_offsets = nullptr;
+    int *d_counter = nullptr;
+    int batch_workgroups = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct Key {
+        const double *mass, *dt;
+        double *pos, *vel, *deriv;
+        int n_steps, n_iter, workgroups;
+        bool operator==(const Key &o) const
+        {
+            return mass == o.mass && dt == o.dt && pos == o.pos && vel == o.vel && deriv == o.deriv &&
+                   n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups;
+        }
+    } key{};
+};
+
+namespace {
+
+const char *kNoCtxMsg = "hermite: null context";
+
+hermite_status fail(hermite_ctx *ctx, hermite_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+hermite_status hip_fail(hermite_ctx *ctx, hipError_t e, const char *where)
+{
+    std::string m = std::string("hermite: HIP error in ") + where + ": " + hipGetErrorString(e);
+    return fail(ctx, HERMITE_E_HIP, m);
+}
+
+#define HIP_TRY(ctx, expr, where)                  \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+hermite_status check_params(const hermite_params *prm, std::string &msg)
+{
+    if (!prm) { msg = "hermite: params is NULL"; return HERMITE_E_ARG; }
+    if (prm->order != 4 && prm->order != 6 && prm->order != 8) {
+        msg = "hermite: order must be 4, 6 or 8";
+        return HERMITE_E_ORDER;
+    }
+    if (prm->precision != HERMITE_FP64 && prm->precision != HERMITE_MIXED) {
+        msg = "hermite: precision must be HERMITE_FP64 or HERMITE_MIXED";
+        return HERMITE_E_ARG;
+    }
+    if (prm->corrector < 0 || prm->corrector > 2) { msg = "hermite: unknown corrector"; return HERMITE_E_ARG; }
+    if (!std::isfinite(prm->G)) { msg = "hermite: G must be finite"; return HERMITE_E_ARG; }
+    if (!std::isfinite(prm->eps2) || prm->eps2 < 0.0) { msg = "hermite: eps2 must be finite and >= 0"; return HERMITE_E_ARG; }
+    return HERMITE_OK;
+}
+
+hermite_status check_state(hermite_ctx *ctx, const hermite_state *s, bool need_init, bool need_pred_eval)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!s) return fail(ctx, HERMITE_E_ARG, "hermite: state is NULL");
+    if (s->n < 0 || s->n > ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n outside [0, n_max]");
+    if (s->n > 0) {
+        if (!s->mass || !s->pos || !s->vel || !s->deriv)
+            return fail(ctx, HERMITE_E_ARG, "hermite: state has a NULL mass/pos/vel/deriv pointer");
+        if (need_pred_eval && (!s->pred || !s->eval))
+            return fail(ctx, HERMITE_E_ARG, "hermite: state has a NULL pred/eval pointer");
+    }
+    if (need_init && !s->initialized) return fail(ctx, HERMITE_E_STATE, "hermite: state not initialised (hermite_init)");
+    return HERMITE_OK;
+}
+
+bool good_dt(double dt) { return std::isfinite(dt) && dt != 0.0; }
+
+int64_t partial_capacity(int64_t n_max, int p)
+{
+    // split partial sums of up to p+1 derivative blocks; enough for the automatic
+    // split at any n <= n_max (n * auto_split(n) is at most ~ 1024 * kBlock + n).
+    const int64_t nv = p + 1;
+    int64_t ns = std::min<int64_t>(64, hermite::auto_split(n_max, 1));
+    int64_t elems = std::max<int64_t>(n_max * ns, (int64_t)1100 * hermite::kBlock);
+    if (n_max == 0) elems = 0;
+    return nv * 3 * elems;
+}
+
+hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
+                         const double *const *path, double *out, int ipt, int nsplit, int jsource)
+{
+    ForceArgs a{};
+    a.n = s->n;
+    a.mass = s->mass;
+    for (int k = 0; k <= K; ++k) a.path[k] = path[k];
+    a.K = K;
+    a.k_first = k_first;
+    a.G = ctx->prm.G;
+    a.eps2 = ctx->prm.eps2;
+    a.out = out;
+    a.partial = ctx->partial;
+    a.partial_cap = ctx->partial_cap;
+    a.jsource = jsource == 1 ? hermite::JSource::Scalar : hermite::JSource::Lds;
+    a.jrec = ctx->jrec;
+    if (nsplit <= 0) nsplit = hermite::auto_split(s->n, ipt);
+    HIP_TRY(ctx, hermite::launch_force(a, chain, ipt, nsplit, ctx->stream), "force kernel launch");
+    return HERMITE_OK;
+}
+
+hermite_status check_finite(hermite_ctx *ctx, const double *const *arrays, const int64_t *counts, int narr)
+{
+    HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream), "finite-flag clear");
+    for (int i = 0; i < narr; ++i)
+        HIP_TRY(ctx, hermite::launch_check_finite(arrays[i], counts[i], ctx->flag, ctx->stream), "finite check");
+    int h = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "finite-flag copy");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "finite-flag sync");
+    if (h) return fail(ctx, HERMITE_E_NONFINITE, "hermite: non-finite value in the state");
+    return HERMITE_OK;
+}
+
+void free_ctx(hermite_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->partial) (void)hipFree(ctx->partial);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->d_bin_start) (void)hipFree(ctx->d_bin_start);
+    if (ctx->d_bin_sys) (void)hipFree(ctx->d_bin_sys);
+    if (ctx->d_offsets) (void)hipFree(ctx->d_offsets);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->jrec) (void)hipFree(ctx->jrec);
+    delete ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hermite_version(void) { return "paper_2006_02501_amd hermite 0.1 (gfx950)"; }
+
+const char *hermite_last_error(const hermite_ctx *ctx) { return ctx ? ctx->err.c_str() : kNoCtxMsg; }
+
+hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hip_stream, hermite_ctx **out)
+{
+    std::string msg;
+    if (!out) return HERMITE_E_ARG;
+    *out = nullptr;
+    hermite_status st = check_params(prm, msg);
+    if (st != HERMITE_OK) return st;
+    if (n_max < 0) return HERMITE_E_ARG;
+    hermite_ctx *ctx = new hermite_ctx();
+    ctx->prm = *prm;
+    ctx->p = prm->order / 2 - 1;
+    ctx->n_max = n_max;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->partial_cap = partial_capacity(n_max, ctx->p);
+    if (ctx->partial_cap > 0 && hipMalloc((void **)&ctx->partial, ctx->partial_cap * sizeof(double)) != hipSuccess) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    if (hipMalloc((void **)&ctx->flag, sizeof(int)) != hipSuccess) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    if (n_max > 0 &&
+        hipMalloc((void **)&ctx->jrec, (size_t)n_max * hermite::kJRecDoubles * sizeof(double)) != hipSuccess) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    *out = ctx;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_destroy(hermite_ctx *ctx)
+{
+    free_ctx(ctx);
+    return HERMITE_OK;
+}
+
+hermite_status hermite_set_stream(hermite_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (i_per_thread != 1 && i_per_thread != 2)
+        return fail(ctx, HERMITE_E_ARG, "hermite: i_per_thread must be 1 or 2");
+    if (j_split < 0 || j_split > 64) return fail(ctx, HERMITE_E_ARG, "hermite: j_split must be in 0..64");
+    if (j_source != 0 && j_source != 1) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0 or 1");
+    ctx->ipt = i_per_thread;
+    ctx->nsplit = j_split;
+    ctx->jsource = j_source;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context, use hermite_batch_init");
+    hermite_status st = check_state(ctx, s, false, false);
+    if (st != HERMITE_OK) return st;
+    const int p = ctx->p;
+    const int64_t n3 = 3 * s->n;
+    if (s->n > 0) {
+        // pass 1: a, adot from (x, v)
+        const double *path[hermite::kMaxPath] = {s->pos, s->vel};
+        st = run_force(ctx, s, Chain::Generic, 1, 0, path, s->deriv, 1, 0, 0);
+        if (st != HERMITE_OK) return st;
+        if (p >= 2) {   // pass 2: a^(2), a^(3) from (x, v, a, adot)
+            const double *path2[hermite::kMaxPath] = {s->pos, s->vel, s->deriv, s->deriv + n3};
+            st = run_force(ctx, s, Chain::Generic, 3, 2, path2, s->deriv + 2 * n3, 1, 0, 0);
+            if (st != HERMITE_OK) return st;
+        }
+        if (p >= 3) {   // pass 3: a^(4), a^(5) from (x, v, a, ..., a^(3))
+            const double *path3[hermite::kMaxPath] = {s->pos, s->vel, s->deriv, s->deriv + n3,
+                                                      s->deriv + 2 * n3, s->deriv + 3 * n3};
+            st = run_force(ctx, s, Chain::Generic, 5, 4, path3, s->deriv + 4 * n3, 1, 0, 0);
+            if (st != HERMITE_OK) return st;
+        }
+    }
+    s->initialized = 1;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
+    hermite_status st = check_state(ctx, s, true, true);
+    if (st != HERMITE_OK) return st;
+    HIP_TRY(ctx, hermite::launch_predict(ctx->p, s->n, dt, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
+            "predict launch");
+    return HERMITE_OK;
+}
+
+hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    hermite_status st = check_state(ctx, s, false, true);
+    if (st != HERMITE_OK) return st;
+    const int p = ctx->p;
+    const int64_t n3 = 3 * s->n;
+    const double *path[hermite::kMaxPath] = {};
+    for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
+    const Chain ch = ctx->prm.precision == HERMITE_MIXED ? Chain::Mixed : Chain::Fp64;
+    return run_force(ctx, s, ch, p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource);
+}
+
+hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
+    hermite_status st = check_state(ctx, s, true, true);
+    if (st != HERMITE_OK) return st;
+    HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, s->pos, s->vel,
+                                         s->deriv, s->eval, s->pred, ctx->stream),
+            "correct launch");
+    if (last_iter) s->t += dt;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32_t n_iter)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context, use hermite_batch_run");
+    if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
+    if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
+    hermite_status st = check_state(ctx, s, true, true);
+    if (st != HERMITE_OK) return st;
+    st = hermite_predict(ctx, s, dt);
+    for (int it = 0; it < n_iter && st == HERMITE_OK; ++it) {
+        st = hermite_force_derivs(ctx, s);
+        if (st == HERMITE_OK) st = hermite_correct(ctx, s, dt, it == n_iter - 1);
+    }
+    if (st != HERMITE_OK || !ctx->prm.check_finite || s->n == 0) return st;
+    const double *arrs[3] = {s->pos, s->vel, s->deriv};
+    const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
+    return check_finite(ctx, arrs, cnt, 3);
+}
+
+hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, double *phi)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    hermite_status st = check_state(ctx, s, false, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n > 0 && !phi) return fail(ctx, HERMITE_E_ARG, "hermite: phi is NULL");
+    HIP_TRY(ctx, hermite::launch_potential(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, phi, ctx->stream),
+            "potential launch");
+    return HERMITE_OK;
+}
+
+hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_per_thread, int32_t *j_split,
+                                int32_t *j_source)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    hermite_status st = check_state(ctx, s, false, true);
+    if (st != HERMITE_OK) return st;
+    int best_ipt = 1, best_split = 0, best_src = 1;
+    if (s->n > 0) {
+        hipEvent_t e0, e1;
+        HIP_TRY(ctx, hipEventCreate(&e0), "event create");
+        HIP_TRY(ctx, hipEventCreate(&e1), "event create");
+        float best = 1e30f;
+        for (int src = 0; src <= 1 && st == HERMITE_OK; ++src) {
+            for (int ipt = 1; ipt <= 2 && st == HERMITE_OK; ++ipt) {
+                const int base = hermite::auto_split(s->n, ipt);
+                std::vector<int> cands = {base};
+                for (int f : {2, 4}) {
+                    if (base * f <= 64) cands.push_back(base * f);
+                    if (base / f >= 1) cands.push_back(base / f);
+                }
+                std::sort(cands.begin(), cands.end());
+                cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+                for (int ns : cands) {
+                    ctx->ipt = ipt;
+                    ctx->nsplit = ns;
+                    ctx->jsource = src;
+                    st = hermite_force_derivs(ctx, s);   // warm-up
+                    if (st != HERMITE_OK) break;
+                    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream), "event record");
+                    for (int r = 0; r < 3 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
+                    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream), "event record");
+                    HIP_TRY(ctx, hipEventSynchronize(e1), "event sync");
+                    float ms = 0.0f;
+                    HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
+                    if (st == HERMITE_OK && ms < best) {
+                        best = ms;
+                        best_ipt = ipt;
+                        best_split = ns;
+                        best_src = src;
+                    }
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != HERMITE_OK) return st;
+    }
+    ctx->ipt = best_ipt;
+    ctx->nsplit = best_split;
+    ctx->jsource = best_src;
+    if (i_per_thread) *i_per_thread = best_ipt;
+    if (j_split) *j_split = best_split;
+    if (j_source) *j_source = best_src;
+    return HERMITE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+
+hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
+                                    void *hip_stream, hermite_ctx **out)
+{
+    std::string msg;
+    if (!out) return HERMITE_E_ARG;
+    *out = nullptr;
+    hermite_status st = check_params(prm, msg);
+    if (st != HERMITE_OK) return st;
+    if (n_sys < 0 || (n_sys > 0 && !offsets)) return HERMITE_E_ARG;
+    if (n_sys > 0 && offsets[0] != 0) return HERMITE_E_ARG;
+    int32_t max_size = 0;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        const int64_t sz = offsets[i + 1] - offsets[i];
+        if (sz < 1 || sz > 64) return HERMITE_E_ARG;
+        max_size = std::max<int32_t>(max_size, (int32_t)sz);
+    }
+    // First-fit-decreasing packing of systems into 64-lane bins.
+    std::vector<int32_t> order(n_sys);
+    for (int32_t i = 0; i < n_sys; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+    });
+    std::vector<std::vector<int32_t>> bins;
+    std::vector<int32_t> fill;
+    for (int32_t s : order) {
+        const int32_t sz = (int32_t)(offsets[s + 1] - offsets[s]);
+        size_t b = 0;
+        while (b < bins.size() && fill[b] + sz > 64) ++b;
+        if (b == bins.size()) {
+            bins.emplace_back();
+            fill.push_back(0);
+        }
+        bins[b].push_back(s);
+        fill[b] += sz;
+    }
+    std::vector<int32_t> bin_start(bins.size() + 1, 0), bin_sys;
+    for (size_t b = 0; b < bins.size(); ++b) {
+        bin_start[b + 1] = bin_start[b] + (int32_t)bins[b].size();
+        for (int32_t s : bins[b]) bin_sys.push_back(s);
+    }
+    hermite_ctx *ctx = new hermite_ctx();
+    ctx->prm = *prm;
+    ctx->p = prm->order / 2 - 1;
+    ctx->batch = true;
+    ctx->n_sys = n_sys;
+    ctx->n_bins = (int32_t)bins.size();
+    ctx->max_size = max_size;
+    ctx->offsets.assign(offsets, offsets + (n_sys + 1));
+    ctx->n_max = n_sys > 0 ? offsets[n_sys] : 0;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->batch_workgroups = 0;
+    auto alloc_copy = [&](void **dst, const void *src, size_t bytes) {
+        if (bytes == 0) bytes = 8;
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+        return true;
+    };
+    bool ok = alloc_copy((void **)&ctx->d_bin_start, bin_start.data(), bin_start.size() * sizeof(int32_t)) &&
+              alloc_copy((void **)&ctx->d_bin_sys, bin_sys.empty() ? nullptr : bin_sys.data(),
+                         bin_sys.size() * sizeof(int32_t)) &&
+              alloc_copy((void **)&ctx->d_offsets, ctx->offsets.data(), ctx->offsets.size() * sizeof(int64_t)) &&
+              alloc_copy((void **)&ctx->d_counter, nullptr, sizeof(int)) &&
+              alloc_copy((void **)&ctx->flag, nullptr, sizeof(int));
+    if (!ok) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        free_ctx(ctx);
+        return HERMITE_E_HIP;
+    }
+    *out = ctx;
+    return HERMITE_OK;
+}
+
+static hermite::BatchPlan plan_of(hermite_ctx *ctx)
+{
+    hermite::BatchPlan pl{};
+    pl.n_sys = ctx->n_sys;
+    pl.n_bins = ctx->n_bins;
+    pl.bin_start = ctx->d_bin_start;
+    pl.bin_sys = ctx->d_bin_sys;
+    pl.offsets = ctx->d_offsets;
+    pl.counter = ctx->d_counter;
+    return pl;
+}
+
+hermite_status hermite_batch_init(hermite_ctx *ctx, hermite_state *s)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
+    hermite_status st = check_state(ctx, s, false, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the batch total");
+    HIP_TRY(ctx, hermite::launch_batch_init(plan_of(ctx), ctx->p, s->n, s->mass, s->pos, s->vel, s->deriv,
+                                            ctx->prm.G, ctx->prm.eps2, ctx->stream),
+            "batch init launch");
+    s->initialized = 1;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                 int32_t n_iter)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
+    if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
+    if (n_steps < 0) return fail(ctx, HERMITE_E_ARG, "hermite: n_steps must be >= 0");
+    hermite_status st = check_state(ctx, s, true, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the batch total");
+    if (ctx->n_sys > 0 && !dt_sys) return fail(ctx, HERMITE_E_ARG, "hermite: dt_sys is NULL");
+    if (n_steps == 0 || ctx->n_sys == 0) return HERMITE_OK;
+    int wg = ctx->batch_workgroups;
+    if (wg <= 0) wg = std::min<int>(ctx->n_bins, 256 * 8);
+    hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, n_steps, n_iter, wg};
+    if (!ctx->graph_exec || !(key == ctx->key)) {
+        if (ctx->graph_exec) { (void)hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+        if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+        hipStream_t cs = ctx->capture_stream;
+        HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture begin");
+        hipError_t e1 = hermite::launch_reset_counter(ctx->d_counter, cs);
+        hipError_t e2 = hermite::launch_batch_run(plan_of(ctx), ctx->p, ctx->prm.precision == HERMITE_MIXED,
+                                                  ctx->prm.corrector, s->n, s->mass, s->pos, s->vel, s->deriv,
+                                                  dt_sys, n_steps, n_iter, ctx->prm.G, ctx->prm.eps2, wg, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(cs, &g);
+        if (e1 != hipSuccess) return hip_fail(ctx, e1, "graph capture (counter reset)");
+        if (e2 != hipSuccess) return hip_fail(ctx, e2, "graph capture (batch kernel)");
+        if (e3 != hipSuccess) return hip_fail(ctx, e3, "graph capture end");
+        ctx->graph = g;
+        HIP_TRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
+        ctx->key = key;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream), "graph launch");
+    s->t += n_steps;
+    if (!ctx->prm.check_finite) return HERMITE_OK;
+    const double *arrs[3] = {s->pos, s->vel, s->deriv};
+    const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
+    return check_finite(ctx, arrs, cnt, 3);
+}
+
+}  // extern "C"

@@ -1,0 +1,256 @@
+"""Python binding of ``libhermite.so`` -- argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; PyTorch only
+provides device memory (FP64 tensors, structure-of-arrays) and the HIP stream.
+If the library has not been built this module raises on first use: there is
+no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhermite.so")
+
+HERMITE_OK = 0
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_ORDER", -3: "E_ALLOC", -4: "E_HIP", -5: "E_NONFINITE", -6: "E_STATE"}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+CORRECTORS = {"modified": 0, "beta1": 1, "shifted": 2}
+
+
+class HermiteError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("corrector", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32), ("G", ctypes.c_double), ("eps2", ctypes.c_double)]
+
+
+class StateC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mass", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("vel", ctypes.c_void_p), ("deriv", ctypes.c_void_p), ("pred", ctypes.c_void_p),
+                ("eval", ctypes.c_void_p), ("t", ctypes.c_double), ("initialized", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); mirrors include/hermite.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "hermite_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int64, _P, ctypes.POINTER(_P)]),
+    "hermite_destroy": (ctypes.c_int, [_P]),
+    "hermite_set_stream": (ctypes.c_int, [_P, _P]),
+    "hermite_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
+    "hermite_predict": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double]),
+    "hermite_force_derivs": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
+    "hermite_correct": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
+    "hermite_step": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
+    "hermite_potential": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P]),
+    "hermite_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                            _P, ctypes.POINTER(_P)]),
+    "hermite_batch_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
+    "hermite_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]),
+    "hermite_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hermite_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "hermite_last_error": (ctypes.c_char_p, [_P]),
+    "hermite_version": (ctypes.c_char_p, []),
+}
+
+
+def load_library():
+    """Load libhermite.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhermite.so is not built (%s); run paper_2006_02501_amd/build.py "
+                              "or __graft_entry__.build()" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(ctx, status):
+    if status != HERMITE_OK:
+        msg = load_library().hermite_last_error(ctx)
+        raise HermiteError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class DeviceState:
+    """Particle state of an order-2(p+1) integrator in device memory (FP64, SoA)."""
+
+    def __init__(self, p, mass, x, v, device, t=0.0, with_pred=True):
+        self.p = p
+        dev = torch.device(device)
+        self.mass = torch.as_tensor(np.ascontiguousarray(mass, dtype=np.float64)).to(dev)
+        n = self.mass.shape[0]
+        self.pos = torch.as_tensor(np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(3, n))).to(dev)
+        self.vel = torch.as_tensor(np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(3, n))).to(dev)
+        self.deriv = torch.zeros((2 * p, 3, n), dtype=torch.float64, device=dev)
+        if with_pred:
+            self.pred = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
+            self.eval = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
+        else:
+            self.pred = self.eval = None
+        self.c = StateC()
+        self.c.n = n
+        self.c.mass = self.mass.data_ptr()
+        self.c.pos = self.pos.data_ptr()
+        self.c.vel = self.vel.data_ptr()
+        self.c.deriv = self.deriv.data_ptr()
+        self.c.pred = self.pred.data_ptr() if with_pred else None
+        self.c.eval = self.eval.data_ptr() if with_pred else None
+        self.c.t = float(t)
+        self.c.initialized = 0
+
+    @property
+    def n(self):
+        return self.c.n
+
+    @property
+    def t(self):
+        return self.c.t
+
+    @property
+    def initialized(self):
+        return bool(self.c.initialized)
+
+    def mark_initialized(self):
+        """For a state restored from a checkpoint (t, mass, pos, vel, deriv)."""
+        self.c.initialized = 1
+
+    def host(self):
+        """Copy the state to the host as numpy arrays (synchronises)."""
+        d = dict(mass=self.mass.cpu().numpy(), x=self.pos.cpu().numpy(), v=self.vel.cpu().numpy(),
+                 derivs=[q for q in self.deriv.cpu().numpy()], t=self.t)
+        if self.pred is not None:
+            d["pred"] = [q for q in self.pred.cpu().numpy()]
+            d["eval"] = [q for q in self.eval.cpu().numpy()]
+        return d
+
+
+class Hermite:
+    """One integrator context (hermite_create) bound to a torch device and stream."""
+
+    def __init__(self, order, n_max, precision="fp64", corrector="modified", G=1.0, eps2=0.0,
+                 check_finite=False, device="cuda:0"):
+        self.lib = load_library()
+        self.order = order
+        self.p = order // 2 - 1
+        self.device = torch.device(device)
+        self.prm = Params(order, PRECISIONS[precision], CORRECTORS[corrector], 1 if check_finite else 0,
+                          float(G), float(eps2))
+        self.ctx = ctypes.c_void_p()
+        _check(None, self.lib.hermite_create(ctypes.byref(self.prm), int(n_max), _stream_handle(self.device),
+                                             ctypes.byref(self.ctx)))
+
+    def close(self):
+        if self.ctx:
+            self.lib.hermite_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self, mass, x, v, t=0.0):
+        return DeviceState(self.p, mass, x, v, self.device, t)
+
+    def use_current_stream(self):
+        _check(self.ctx, self.lib.hermite_set_stream(self.ctx, _stream_handle(self.device)))
+
+    def init(self, st):
+        _check(self.ctx, self.lib.hermite_init(self.ctx, ctypes.byref(st.c)))
+
+    def predict(self, st, dt):
+        _check(self.ctx, self.lib.hermite_predict(self.ctx, ctypes.byref(st.c), float(dt)))
+
+    def force_derivs(self, st):
+        _check(self.ctx, self.lib.hermite_force_derivs(self.ctx, ctypes.byref(st.c)))
+
+    def correct(self, st, dt, last_iter):
+        _check(self.ctx, self.lib.hermite_correct(self.ctx, ctypes.byref(st.c), float(dt), 1 if last_iter else 0))
+
+    def step(self, st, dt, n_iter):
+        _check(self.ctx, self.lib.hermite_step(self.ctx, ctypes.byref(st.c), float(dt), int(n_iter)))
+
+    def potential(self, st):
+        phi = torch.empty(st.n, dtype=torch.float64, device=self.device)
+        _check(self.ctx, self.lib.hermite_potential(self.ctx, ctypes.byref(st.c), ctypes.c_void_p(phi.data_ptr())))
+        return phi
+
+    def set_launch(self, i_per_thread, j_split, j_source=1):
+        """j_source: 0 = LDS tiles, 1 = scalar stream (SGPR operands)."""
+        _check(self.ctx, self.lib.hermite_set_launch(self.ctx, int(i_per_thread), int(j_split), int(j_source)))
+
+    def autotune(self, st):
+        ipt, js, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.ctx, self.lib.hermite_autotune(self.ctx, ctypes.byref(st.c), ctypes.byref(ipt), ctypes.byref(js),
+                                                   ctypes.byref(src)))
+        return ipt.value, js.value, src.value
+
+
+class BatchHermite:
+    """Batched form: many independent systems advanced in one persistent launch."""
+
+    def __init__(self, order, offsets, precision="fp64", corrector="modified", G=1.0, eps2=0.0,
+                 check_finite=False, device="cuda:0"):
+        self.lib = load_library()
+        self.order = order
+        self.p = order // 2 - 1
+        self.device = torch.device(device)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.n_sys = self.offsets.shape[0] - 1
+        self.prm = Params(order, PRECISIONS[precision], CORRECTORS[corrector], 1 if check_finite else 0,
+                          float(G), float(eps2))
+        self.ctx = ctypes.c_void_p()
+        _check(None, self.lib.hermite_batch_create(
+            ctypes.byref(self.prm), int(self.n_sys),
+            self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            _stream_handle(self.device), ctypes.byref(self.ctx)))
+
+    def close(self):
+        if self.ctx:
+            self.lib.hermite_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self, mass, x, v):
+        return DeviceState(self.p, mass, x, v, self.device, with_pred=False)
+
+    def init(self, st):
+        _check(self.ctx, self.lib.hermite_batch_init(self.ctx, ctypes.byref(st.c)))
+
+    def run(self, st, dt_sys, n_steps, n_iter):
+        if not isinstance(dt_sys, torch.Tensor):
+            dt_sys = torch.as_tensor(np.asarray(dt_sys, dtype=np.float64))
+        dt_sys = dt_sys.to(device=self.device, dtype=torch.float64).contiguous()
+        self._dt = dt_sys          # keep alive: the captured graph holds its address
+        _check(self.ctx, self.lib.hermite_batch_run(self.ctx, ctypes.byref(st.c), ctypes.c_void_p(dt_sys.data_ptr()),
+                                                    int(n_steps), int(n_iter)))
+        return dt_sys
+
+
+def version():
+    return load_library().hermite_version().decode()

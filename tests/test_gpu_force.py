@@ -1,0 +1,150 @@
+"""GPU parity of the O(N^2) evaluation (hermite_force_derivs), the explicit
+initial derivatives (hermite_init) and the potential, against the oracle,
+element by element, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hermite_oracle as ho
+from paper_2006_02501_amd import Hermite
+from parity_util import TOL_FP64, TOL_MIXED, deriv_error, disc_path, random_path, within
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _eval_gpu(order, mass, path, precision="fp64", eps2=0.0, G=1.0, launch=None):
+    p = order // 2 - 1
+    n = len(mass)
+    h = Hermite(order, max(n, 1), precision=precision, eps2=eps2, G=G, device=DEV)
+    st = h.state(mass, path[0], path[1])
+    for k in range(p + 1):
+        st.pred[k].copy_(torch.as_tensor(np.asarray(path[k], dtype=np.float64).reshape(3, n)))
+    if launch is not None:
+        h.set_launch(*launch)
+    h.force_derivs(st)
+    out = st.eval.cpu().numpy()
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+@pytest.mark.parametrize("n", [2, 63, 257, 1000, 2050])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_derivs_disc(order, n, precision):
+    _say("force_derivs disc order=%d n=%d %s" % (order, n, precision))
+    p = order // 2 - 1
+    w, path = disc_path(n, p)
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, w["mass"], path, precision)
+    err = deriv_error(g, o, mag, None if precision == "fp64" else nat)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    assert within(err, tol), (err.max(axis=1), tol)
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_derivs_random_softened(order, precision):
+    _say("force_derivs random softened order=%d %s" % (order, precision))
+    rng = np.random.default_rng(order)
+    p = order // 2 - 1
+    n = 777
+    mass, path = random_path(rng, n, p)
+    G, eps2 = 0.7, 1e-3
+    o, mag, nat = ho.pair_derivs(mass, path, K=p, G=G, eps2=eps2, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, mass, path, precision, eps2=eps2, G=G)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    err = deriv_error(g, o, mag, None if precision == "fp64" else nat)
+    assert within(err, tol), (err.max(axis=1), tol)
+
+
+@pytest.mark.parametrize("source", [0, 1])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 3), (2, 1), (2, 5), (2, 0), (1, 64)])
+@pytest.mark.parametrize("order", [4, 8])
+def test_force_derivs_launch_shapes(order, shape, source):
+    _say("force_derivs launch shape", order, shape, source)
+    p = order // 2 - 1
+    w, path = disc_path(1500, p)
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, w["mass"], path, "fp64", launch=shape + (source,))
+    assert deriv_error(g, o, mag).max() <= TOL_FP64
+    g = _eval_gpu(order, w["mass"], path, "mixed", launch=shape + (source,))
+    assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
+
+
+def test_force_derivs_single_particle_and_empty():
+    _say("force_derivs n=1 and n=0")
+    g = _eval_gpu(8, np.array([1.0]), [np.ones((3, 1))] * 4)
+    assert np.array_equal(g, np.zeros((4, 3, 1)))
+    h = Hermite(8, 0, device=DEV)
+    st = h.state(np.zeros(0), np.zeros((3, 0)), np.zeros((3, 0)))
+    h.force_derivs(st)
+    h.init(st)
+    h.step(st, 0.1, 2)
+    h.close()
+
+
+def test_force_derivs_bitwise_reproducible():
+    _say("force_derivs reproducibility")
+    w, path = disc_path(3000, 3)
+    a = _eval_gpu(8, w["mass"], path, "fp64")
+    b = _eval_gpu(8, w["mass"], path, "fp64")
+    assert np.array_equal(a, b)
+    c = _eval_gpu(8, w["mass"], path, "mixed")
+    d = _eval_gpu(8, w["mass"], path, "mixed")
+    assert np.array_equal(c, d)
+
+
+def test_force_derivs_full_size_sampled():
+    # Disc of 16384 bodies (8th order) in the launch configuration the
+    # benchmark times; 512 sampled i-particles checked against the oracle.
+    _say("force_derivs N=16384 sampled")
+    n = 16384
+    w, path = disc_path(n, 3)
+    rng = np.random.default_rng(99)
+    il = np.sort(rng.choice(n, 512, replace=False))
+    il[0] = 0                     # the central body
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
+    for precision, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        g = _eval_gpu(8, w["mass"], path, precision)
+        err = deriv_error(g[:, :, il], o, mag, None if precision == "fp64" else nat)
+        _say("  %s max err per order %s" % (precision, err.max(axis=1)))
+        assert within(err, tol), (precision, err.max(axis=1))
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_init_parity(order):
+    _say("init order=%d" % order)
+    p = order // 2 - 1
+    w = disc_path(900, 1)[0]
+    st_o = ho.State(w["mass"], w["x"], w["v"], p)
+    ho.init_derivs(st_o, eps2=1e-6)
+    h = Hermite(order, 900, eps2=1e-6, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    g = st.deriv.cpu().numpy()
+    assert st.initialized
+    for k in range(2 * p):
+        o = st_o.derivs[k]
+        # per-particle relative error of the derivative vector
+        num = np.abs(g[k] - o).max(axis=0)
+        den = np.sqrt((o * o).sum(axis=0))
+        assert (num / den).max() <= 1e-11, (k, (num / den).max())
+    h.close()
+
+
+def test_potential_parity():
+    _say("potential")
+    w, _ = disc_path(1234, 1)
+    h = Hermite(4, 1234, eps2=1e-5, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    phi = h.potential(st).cpu().numpy()
+    o = ho.potential_per_particle(w["mass"], w["x"], eps2=1e-5)
+    assert np.abs(phi - o).max() <= 1e-13 * np.abs(o).max()
+    h.close()

@@ -1,0 +1,304 @@
+"""GPU parity of the per-particle kernels (predict, correct + interpolation),
+of whole P(EC)^n steps and of the batched persistent form, against the oracle;
+plus the paper's physics claims reproduced on the GPU path."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hermite_oracle as ho
+from paper_2006_02501_amd import BatchHermite, Hermite, HermiteError
+from parity_util import disc_path, rel_max
+from workloads import batch_systems, kepler_two_body, ring64
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _random_state(rng, n, p):
+    x = rng.normal(size=(3, n))
+    v = rng.normal(size=(3, n))
+    derivs = [rng.normal(size=(3, n)) * 0.5 ** k for k in range(2 * p)]
+    return x, v, derivs
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_predict_parity(order):
+    _say("predict order=%d" % order)
+    p = order // 2 - 1
+    rng = np.random.default_rng(order)
+    n = 1001
+    x, v, derivs = _random_state(rng, n, p)
+    h = Hermite(order, n, device=DEV)
+    st = h.state(np.ones(n), x, v)
+    st.deriv.copy_(torch.as_tensor(np.stack(derivs)))
+    st.mark_initialized()
+    for dt in (0.07, -0.03):
+        h.predict(st, dt)
+        g = st.pred.cpu().numpy()
+        o = ho.predict(p, dt, x, v, derivs)
+        for k in range(p + 1):
+            assert rel_max(g[k], o[k]) <= 1e-14, (dt, k)
+    h.close()
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+@pytest.mark.parametrize("corrector", ["modified", "beta1", "shifted"])
+def test_correct_parity(order, corrector):
+    _say("correct order=%d %s" % (order, corrector))
+    p = order // 2 - 1
+    rng = np.random.default_rng(10 * order + len(corrector))
+    n = 517
+    x, v, derivs = _random_state(rng, n, p)
+    a1 = [d + 0.01 * rng.normal(size=(3, n)) for d in derivs[: p + 1]]
+    dt = 0.05
+    h = Hermite(order, n, corrector=corrector, device=DEV)
+    st = h.state(np.ones(n), x, v)
+    st.deriv.copy_(torch.as_tensor(np.stack(derivs)))
+    st.eval.copy_(torch.as_tensor(np.stack(a1)))
+    st.mark_initialized()
+    ox, ov = ho.correct(p, dt, x, v, derivs[: p + 1], a1, corrector)
+    # intermediate iteration: next iterate goes to pred
+    h.correct(st, dt, last_iter=False)
+    g = st.pred.cpu().numpy()
+    assert rel_max(g[0], ox) <= 1e-14 and rel_max(g[1], ov) <= 1e-14
+    for m in range(p - 1):
+        assert np.array_equal(g[2 + m], a1[m])
+    # last iteration: state advanced, higher derivatives interpolated
+    h.correct(st, dt, last_iter=True)
+    d = st.host()
+    assert rel_max(d["x"], ox) <= 1e-14 and rel_max(d["v"], ov) <= 1e-14
+    assert d["t"] == pytest.approx(dt)
+    for k in range(p + 1):
+        assert np.array_equal(d["derivs"][k], a1[k])
+    hi = ho.interpolate_higher(p, dt, derivs[: p + 1], a1)
+    for m, q in enumerate(hi):
+        # the closed forms cancel heavily (a difference of O(1) values divided
+        # by dt^k); compare against the size of the cancelling terms
+        scale = max(np.abs(a1[0]).max(), np.abs(derivs[0]).max()) * 1e4 / dt ** (p + 1 + m)
+        assert np.abs(d["derivs"][p + 1 + m] - q).max() <= 1e-12 * scale, m
+    h.close()
+
+
+def _run_pair(order, w, dt, n_iter, steps, corrector="modified", eps2=0.0, precision="fp64"):
+    p = order // 2 - 1
+    st_o = ho.State(w["mass"], w["x"], w["v"], p)
+    ho.init_derivs(st_o, eps2=eps2)
+    n = len(w["mass"])
+    h = Hermite(order, n, precision=precision, corrector=corrector, eps2=eps2, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    for _ in range(steps):
+        ho.step(st_o, dt, n_iter, corrector, eps2=eps2)
+        h.step(st, dt, n_iter)
+    d = st.host()
+    h.close()
+    return st_o, d
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_step_parity_kepler(order):
+    _say("step kepler order=%d" % order)
+    w = kepler_two_body(e=0.5)
+    o, g = _run_pair(order, w, w["period"] / 200, 3, 1)
+    assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+    o, g = _run_pair(order, w, w["period"] / 200, 3, 100)
+    assert rel_max(g["x"], o.x) <= 1e-10 and rel_max(g["v"], o.v) <= 1e-10
+    assert g["t"] == pytest.approx(o.t)
+
+
+def test_step_parity_ring64():
+    _say("step ring64")
+    w = ring64()
+    o, g = _run_pair(4, w, w["dt"], w["n_iter"], 1)
+    assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+    o, g = _run_pair(4, w, w["dt"], w["n_iter"], 100)
+    assert rel_max(g["x"], o.x) <= 1e-10 and rel_max(g["v"], o.v) <= 1e-10
+
+
+@pytest.mark.parametrize("order", [6, 8])
+def test_step_parity_disc(order):
+    _say("step disc order=%d" % order)
+    w, _ = disc_path(700, 1)
+    dt = 2 * np.pi / 2000
+    o, g = _run_pair(order, w, dt, 3, 1)
+    assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+    o, g = _run_pair(order, w, dt, 3, 10)
+    assert rel_max(g["x"], o.x) <= 1e-11 and rel_max(g["v"], o.v) <= 1e-11
+    for k in range(order // 2):
+        assert rel_max(g["derivs"][k], o.derivs[k]) <= 1e-9, k
+
+
+def test_mixed_step_close_to_fp64():
+    # A relative force error delta (1e-6 bar) on |a| <= 100 (r >= 0.1) over
+    # T = 5 dt moves v by <= delta |a| T and x by <= delta |a| T^2 / 2:
+    # 1.6e-6 / 3 (max |v| ~ 3) and 1.2e-8 (max |x| ~ 1).
+    _say("mixed step vs fp64")
+    w, _ = disc_path(700, 1)
+    dt = 2 * np.pi / 2000
+    o, g = _run_pair(8, w, dt, 3, 5, precision="mixed")
+    assert rel_max(g["x"], o.x) <= 1.2e-8 and rel_max(g["v"], o.v) <= 5e-7
+
+
+def test_kepler_periapsis_on_gpu():
+    # Sec. 3.1 set-up (a = 1, e = 0.1, dt = 2^-4, n = 3, eps = 1e-8), 10 orbits:
+    # the modified corrector's periapsis drift is far below beta = 1's.
+    _say("kepler periapsis gpu")
+    w = kepler_two_body(e=0.1)
+    steps = int(round(10 * 2 * np.pi / 2 ** -4))
+    res = {}
+    for corr in ("modified", "beta1"):
+        h = Hermite(4, 2, corrector=corr, eps2=1e-16, device=DEV)
+        st = h.state(w["mass"], w["x"], w["v"])
+        h.init(st)
+        d0 = st.host()
+        _, _, om0 = ho.kepler_elements(d0["mass"], d0["x"], d0["v"], 1)
+        for _ in range(steps):
+            h.step(st, 2 ** -4, 3)
+        d = st.host()
+        _, _, om = ho.kepler_elements(d["mass"], d["x"], d["v"], 1)
+        res[corr] = ho.wrap_angle(om - om0)
+        h.close()
+    assert abs(res["modified"]) < 0.01 * abs(res["beta1"])
+
+
+def test_step_errors_and_nonfinite():
+    _say("step errors")
+    h = Hermite(8, 4, check_finite=True, device=DEV)
+    x = np.zeros((3, 2))
+    st = h.state(np.ones(2), x, np.zeros((3, 2)))     # coincident bodies, eps = 0
+    with pytest.raises(HermiteError) as ei:
+        h.step(st, 0.1, 2)
+    assert ei.value.status == -6                     # not initialised
+    h.init(st)
+    with pytest.raises(HermiteError) as ei:
+        h.step(st, 0.1, 2)
+    assert ei.value.status == -5                     # non-finite
+    with pytest.raises(HermiteError) as ei:
+        h.step(st, 0.1, 0)
+    assert ei.value.status == -1
+    with pytest.raises(HermiteError) as ei:
+        h.step(st, float("nan"), 1)
+    assert ei.value.status == -1
+    h.close()
+
+
+def test_checkpoint_resume_bitwise_gpu():
+    _say("checkpoint resume gpu")
+    w, _ = disc_path(500, 1)
+    dt = 2 * np.pi / 2000
+    h = Hermite(8, 500, device=DEV)
+    a = h.state(w["mass"], w["x"], w["v"])
+    h.init(a)
+    for _ in range(6):
+        h.step(a, dt, 3)
+    b = h.state(w["mass"], w["x"], w["v"])
+    h.init(b)
+    for _ in range(3):
+        h.step(b, dt, 3)
+    snap = b.host()
+    c = h.state(snap["mass"], snap["x"], snap["v"], t=snap["t"])
+    c.deriv.copy_(torch.as_tensor(np.stack(snap["derivs"])))
+    c.mark_initialized()
+    for _ in range(3):
+        h.step(c, dt, 3)
+    da, dc = a.host(), c.host()
+    assert np.array_equal(da["x"], dc["x"]) and np.array_equal(da["v"], dc["v"])
+    assert all(np.array_equal(p, q) for p, q in zip(da["derivs"], dc["derivs"]))
+    h.close()
+
+
+def _subset(wb, systems):
+    offs = wb["offsets"]
+    idx = np.concatenate([np.arange(offs[s], offs[s + 1]) for s in systems])
+    sizes = [offs[s + 1] - offs[s] for s in systems]
+    return dict(mass=wb["mass"][idx], x=wb["x"][:, idx], v=wb["v"][:, idx],
+                offsets=np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64), dt=wb["dt"][systems])
+
+
+@pytest.fixture(scope="module")
+def batch_workload():
+    return batch_systems()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_oracle(batch_workload, precision):
+    _say("batch vs oracle %s" % precision)
+    rng = np.random.default_rng(4)
+    systems = np.sort(rng.choice(len(batch_workload["dt"]), 24, replace=False))
+    sub = _subset(batch_workload, systems)
+    bh = BatchHermite(8, sub["offsets"], precision=precision, device=DEV)
+    st = bh.state(sub["mass"], sub["x"], sub["v"])
+    bh.init(st)
+    steps = 20
+    bh.run(st, sub["dt"], steps, 3)
+    d = st.host()
+    bh.close()
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    for s in range(len(systems)):
+        lo, hi = sub["offsets"][s], sub["offsets"][s + 1]
+        o = ho.State(sub["mass"][lo:hi], sub["x"][:, lo:hi], sub["v"][:, lo:hi], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, sub["dt"][s], 3)
+        assert rel_max(d["x"][:, lo:hi], o.x) <= tol, s
+        assert rel_max(d["v"][:, lo:hi], o.v) <= tol * 10, s
+
+
+def test_batch_init_matches_single(batch_workload):
+    _say("batch init vs single-system init")
+    sub = _subset(batch_workload, np.arange(40))
+    bh = BatchHermite(8, sub["offsets"], device=DEV)
+    st = bh.state(sub["mass"], sub["x"], sub["v"])
+    bh.init(st)
+    g = st.deriv.cpu().numpy()
+    bh.close()
+    for s in range(40):
+        lo, hi = sub["offsets"][s], sub["offsets"][s + 1]
+        o = ho.State(sub["mass"][lo:hi], sub["x"][:, lo:hi], sub["v"][:, lo:hi], 3)
+        ho.init_derivs(o)
+        for k in range(6):
+            assert rel_max(g[k][:, lo:hi], o.derivs[k]) <= 1e-11, (s, k)
+
+
+def test_batch_graph_replay_and_bitwise_vs_single(batch_workload):
+    # Replays of the captured graph continue the run exactly: 2 x 5 steps equal
+    # 10 steps, and the batched FP64 kernel equals per-system hermite_step runs
+    # to rounding.
+    _say("batch graph replay")
+    sub = _subset(batch_workload, np.arange(100, 164))
+    bh = BatchHermite(8, sub["offsets"], device=DEV)
+    a = bh.state(sub["mass"], sub["x"], sub["v"])
+    bh.init(a)
+    b = bh.state(sub["mass"], sub["x"], sub["v"])
+    bh.init(b)
+    dt = torch.as_tensor(sub["dt"]).to(DEV)
+    bh.run(a, dt, 10, 3)
+    bh.run(b, dt, 5, 3)
+    torch.cuda.synchronize()
+    bh.run(b, dt, 5, 3)
+    da, db = a.host(), b.host()
+    assert np.array_equal(da["x"], db["x"]) and np.array_equal(da["v"], db["v"])
+    bh.close()
+    for s in range(0, 64, 9):
+        lo, hi = sub["offsets"][s], sub["offsets"][s + 1]
+        h = Hermite(8, hi - lo, device=DEV)
+        st = h.state(sub["mass"][lo:hi], sub["x"][:, lo:hi], sub["v"][:, lo:hi])
+        h.init(st)
+        for _ in range(10):
+            h.step(st, sub["dt"][s], 3)
+        d = st.host()
+        h.close()
+        assert rel_max(da["x"][:, lo:hi], d["x"]) <= 1e-12, s
+
+
+def test_batch_rejects_bad_layout():
+    with pytest.raises(HermiteError):
+        BatchHermite(8, np.array([0, 70]), device=DEV)      # system larger than 64
+    with pytest.raises(HermiteError):
+        BatchHermite(8, np.array([0, 3, 3]), device=DEV)    # empty system

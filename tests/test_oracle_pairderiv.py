@@ -80,6 +80,28 @@ def test_circular_orbit_closed_form():
         assert np.allclose(out[k, :, 0], exp, rtol=0, atol=1e-14 * max(1.0, om ** k))
 
 
+def test_natural_scale_circular_orbit():
+    # On a circular relative orbit every rate |r^(k)|/R equals omega^k, so the
+    # natural scale of the k-th derivative is G m / R^2 omega^k exactly; with
+    # softening the distance is sqrt(R^2 + eps^2).
+    R, om, G, mj, K = 1.7, 0.8, 1.3, 2.5, 5
+    mass = np.array([1.0, mj])
+    path = []
+    for k in range(K + 1):
+        pk = np.zeros((3, 2))
+        pk[0, 1] = R * om ** k * np.cos(k * np.pi / 2)
+        pk[1, 1] = R * om ** k * np.sin(k * np.pi / 2)
+        path.append(pk)
+    _, nat = ho.pair_derivs(mass, path, K=K, G=G, with_scale=True)
+    assert np.allclose(nat[:, 0], [G * mj / R ** 2 * om ** k for k in range(K + 1)], rtol=1e-13)
+    eps2 = 0.3
+    _, nat = ho.pair_derivs(mass, path, K=K, G=G, eps2=eps2, with_scale=True)
+    s = np.sqrt(R * R + eps2)
+    rate = [(R * om ** k / s) ** (1.0 / k) for k in range(1, K + 1)]
+    ome = max(rate)
+    assert np.allclose(nat[:, 0], [G * mj / s ** 2 * ome ** k for k in range(K + 1)], rtol=1e-13)
+
+
 def test_force_is_minus_gradient_of_potential():
     rng = np.random.default_rng(7)
     n = 6
