@@ -1,16 +1,18 @@
 """Benchmark of the modified Hermite hot path on one MI355X.
 
-Workload: stellar disc of 16384 bodies around a central mass (8th order,
-P(EC)^3, dt = 2 pi / 2000; synthetic, seeded).  A timed step is one whole
-P(EC)^3 step (predict, 3 x (evaluate a, adot, a^(2), a^(3) ; correct),
-interpolate) with the state already in HBM.  Metric: pair interactions per
-second, n_iter * N (N - 1) per step, in FP64 and in mixed precision.
+Workload (headline): stellar disc of 16384 bodies around a central mass,
+8th-order modified Hermite, P(EC)^3, dt = 2 pi / 2000 (synthetic, seeded).
+A timed step is one whole P(EC)^3 step -- predict, 3 x (evaluate a, adot,
+a^(2), a^(3); correct), interpolate -- with the state already in HBM.
+Metric: pair interactions per second, n_iter * N (N - 1) per step.  The
+top-level line is the FP64 path; the mixed-precision path is reported beside
+it with its error against the FP64 run.  The batched workload (4096 systems
+of 3..64 bodies, 1000 steps) is reported against one launch per system.
 
-Prints ONE JSON line (rank 0, N = 1 GPU only).
+Prints ONE JSON line (N = 1 GPU only).
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -21,15 +23,55 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import hashlib
+
 FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}     # MI355X vector FP64 / FP32 (published)
+# Sources that determine the evaluation kernels and their launch (split
+# workspace); the measured HBM traffic below is reported only while their
+# hash and the launch shape match what was profiled.
+KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/pair_chain.h",
+                  "paper_2006_02501_amd/csrc/kernels.h", "paper_2006_02501_amd/csrc/runtime.cpp"]
+# HBM bytes per evaluation launch (force kernel + split reduction), from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
+# each scaled by the counter's reading for a 256 MiB device copy.
+MEASURED_TRAFFIC = None
+# MI355X published vector peaks: 256 CUs x 4 SIMD16 x 2 flops (FMA) x 2.4 GHz
+# = 78.6 TFLOP/s FP64; FP32 twice that (157.3) with packed-FP32 issue.
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_mode(precision, w, steps, warmup, autotune=True):
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, launch):
+    """Bytes per launch measured by the counter runs, or None when the kernel
+    sources or the launch shape differ from what was profiled."""
+    t = (MEASURED_TRAFFIC or {}).get(precision)
+    if not t or t["sources_sha256"] != kernel_sources_hash() or t["launch"] != launch:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
+def _energy(h, st):
+    import torch
+
+    phi = h.potential(st)
+    m = st.mass
+    kin = 0.5 * torch.sum(m * torch.sum(st.vel * st.vel, dim=0))
+    pot = 0.5 * torch.sum(m * phi)
+    return float(kin + pot)
+
+
+def time_mode(precision, w, steps, warmup, autotune=True, launch=None):
     import torch
     from paper_2006_02501_amd import Hermite
 
@@ -39,15 +81,18 @@ def time_mode(precision, w, steps, warmup, autotune=True):
     st = h.state(w["mass"], w["x"], w["v"])
     h.init(st)
     shape = None
-    if autotune:
+    if launch is not None:
+        h.set_launch(*launch)
+        shape = tuple(launch)
+    elif autotune:
         h.predict(st, dt)
         shape = h.autotune(st)
     torch.cuda.synchronize()
-    E0 = _energy(h, st, w)
+    E0 = _energy(h, st)
     for _ in range(warmup):
         h.step(st, dt, n_iter)
     torch.cuda.synchronize()
-    # Timed region: K whole steps.  The evaluation is bracketed by events on
+    # Timed region: K whole steps.  Each evaluation is bracketed by events on
     # the same (torch current) stream the library launches on.
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps * n_iter)]
@@ -65,31 +110,41 @@ def time_mode(precision, w, steps, warmup, autotune=True):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     eval_ms = [a.elapsed_time(b) for a, b in evs]
-    E1 = _energy(h, st, w)
+    E1 = _energy(h, st)
+    final = st.host()
     h.close()
     inter = n * (n - 1)
     avg_eval_s = float(np.mean(eval_ms)) / 1e3
-    return dict(
+    flops = FLOPS_PER_INTERACTION[order] * inter
+    achieved = flops / avg_eval_s / 1e12
+    res = dict(
         value=steps * n_iter * inter / elapsed,
         ms_per_step=elapsed / steps * 1e3,
         eval_ms_avg=avg_eval_s * 1e3,
         eval_ms_median=float(np.median(eval_ms)),
         eval_interactions_per_s=inter / avg_eval_s,
-        launch={"i_per_thread": shape[0], "j_split": shape[1], "j_source": ["lds", "scalar"][shape[2]]}
-        if shape else None,
+        launch=({"i_per_thread": shape[0], "j_split": shape[1], "j_source": ["lds", "scalar"][shape[2]],
+                 "wg_waves": shape[3]} if shape else None),
         energy_rel_change=(E1 - E0) / abs(E0),
-        flops_per_eval=FLOPS_PER_INTERACTION[order] * inter,
+        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK_TFLOPS[precision]},
     )
+    res["roofline"]["traffic"] = measured_traffic(precision, res["launch"])
+    return res, final
 
 
-def _energy(h, st, w):
-    import torch
+def orbit_diffs(a, b, n_bodies=256):
+    """Eccentricity-vector and periapsis differences between two final states
+    for the first n_bodies stars relative to the central body."""
+    from oracle import hermite_oracle as ho
 
-    phi = h.potential(st)
-    m = st.mass
-    kin = 0.5 * torch.sum(m * torch.sum(st.vel * st.vel, dim=0))
-    pot = 0.5 * torch.sum(m * phi)
-    return float(kin + pot)
+    de, dw = 0.0, 0.0
+    for k in range(1, n_bodies + 1):
+        ea, _, wa = ho.kepler_elements(a["mass"], a["x"], a["v"], k)
+        eb, _, wb = ho.kepler_elements(b["mass"], b["x"], b["v"], k)
+        de = max(de, float(np.sqrt(((ea - eb) ** 2).sum())))
+        dw = max(dw, abs(ho.wrap_angle(wa - wb)))
+    return de, dw
 
 
 def cpu_baseline(w, target_s=12.0):
@@ -124,6 +179,77 @@ def cpu_baseline(w, target_s=12.0):
                        % (reps, m_i, n, total))
 
 
+def batched(steps, baseline_systems=64, baseline_steps=10):
+    """4096 systems of 3..64 bodies, 8th order, P(EC)^3, per-system dt, in one
+    persistent graph-captured launch; against hermite_step on each system."""
+    import torch
+    from paper_2006_02501_amd import BatchHermite, Hermite
+    from workloads import batch_systems
+
+    wb = batch_systems()
+    offs = wb["offsets"]
+    sizes = np.diff(offs)
+    n_iter = wb["n_iter"]
+    inter_eval = int(np.sum(sizes * (sizes - 1)))
+    out = {"n_systems": int(len(sizes)), "bodies": int(offs[-1]), "steps": steps, "n_iter": n_iter,
+           "interactions_per_eval": inter_eval}
+    dt = torch.as_tensor(wb["dt"]).to("cuda:0")
+    for prec in ("fp64", "mixed"):
+        bh = BatchHermite(8, offs, precision=prec, device="cuda:0")
+        st = bh.state(wb["mass"], wb["x"], wb["v"])
+        bh.init(st)
+        bh.run(st, dt, steps, n_iter)          # graph capture + warm-up
+        torch.cuda.synchronize()
+        bh.init(st)                            # same buffers: the captured graph is replayed
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bh.run(st, dt, steps, n_iter)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        bh.close()
+        out[prec] = {"ms": ms, "interactions_per_s": steps * n_iter * inter_eval / (ms / 1e3)}
+    # one launch sequence per system (hermite_step), a sample, extrapolated
+    pick = np.linspace(0, len(sizes) - 1, baseline_systems).astype(int)
+    t_total = 0.0
+    inter_sample = 0
+    for s in pick:
+        lo, hi = offs[s], offs[s + 1]
+        h = Hermite(8, hi - lo, device="cuda:0")
+        st = h.state(wb["mass"][lo:hi], wb["x"][:, lo:hi], wb["v"][:, lo:hi])
+        h.init(st)
+        h.step(st, wb["dt"][s], n_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(baseline_steps):
+            h.step(st, wb["dt"][s], n_iter)
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        inter_sample += baseline_steps * n_iter * int((hi - lo) * (hi - lo - 1))
+        h.close()
+    rate = inter_sample / t_total
+    out["per_system_launches"] = {"interactions_per_s": rate,
+                                  "sample": "%d systems x %d steps, hermite_step per system, extrapolated"
+                                            % (baseline_systems, baseline_steps),
+                                  "extrapolated_ms": steps * n_iter * inter_eval / rate * 1e3}
+    out["speedup_fp64_vs_per_system"] = out["fp64"]["interactions_per_s"] / rate
+    return out
+
+
+def calibrate_copy(mib=256, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +257,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch shapes instead of autotuning, e.g. 'fp64=2,16,0,4;mixed=1,1,1,16' "
+                         "(i_per_thread, j_split, j_source, wg_waves)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the kernel at one GPU's share); "
@@ -139,19 +271,24 @@ def main():
     import torch  # noqa: F401
     from workloads import disc16k
 
+    calib = calibrate_copy() if args.calibrate_copy else None
     w = disc16k()
     n = len(w["mass"])
     log("bench: disc N=%d order=%d n_iter=%d steps=%d warmup=%d" % (n, w["order"], w["n_iter"], args.steps,
                                                                      args.warmup))
-    res = {}
+    fixed = {}
+    if args.launch:
+        for part in args.launch.split(";"):
+            k, v = part.split("=")
+            fixed[k.strip()] = tuple(int(x) for x in v.split(","))
+    res, fin = {}, {}
     for prec in ("fp64", "mixed"):
-        res[prec] = time_mode(prec, w, args.steps, args.warmup, autotune=not args.no_autotune)
-        log("  %s: %.3e interactions/s, %.3f ms/step, eval %.3f ms" % (prec, res[prec]["value"],
-                                                                        res[prec]["ms_per_step"],
-                                                                        res[prec]["eval_ms_avg"]))
-    main_mode = "fp64"
-    r = res[main_mode]
-    achieved = r["flops_per_eval"] / (r["eval_ms_avg"] / 1e3) / 1e12
+        res[prec], fin[prec] = time_mode(prec, w, args.steps, args.warmup, autotune=not args.no_autotune,
+                                         launch=fixed.get(prec))
+        log("  %s: %.3e interactions/s, %.3f ms/step, eval %.3f ms, launch %s"
+            % (prec, res[prec]["value"], res[prec]["ms_per_step"], res[prec]["eval_ms_avg"], res[prec]["launch"]))
+    r, mx = res["fp64"], res["mixed"]
+    de, dw = orbit_diffs(fin["fp64"], fin["mixed"])
     out = {
         "metric": "pair interactions/sec for 8th-order derivs at N=16k: mixed vs FP64, 1 GPU",
         "value": r["value"],
@@ -165,19 +302,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "disc16k: central mass 1 + 16383 stars of 1e-7, 8th-order modified Hermite, "
-                               "P(EC)^3, dt=2pi/2000, G=1, eps=0", "n_bodies": n, "order": 8, "n_iter": 3},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[main_mode], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[main_mode], "traffic": None,
-                     "kernel": "force_kernel<K=3,FP64> (+ split reduction)",
-                     "flops_per_interaction": FLOPS_PER_INTERACTION[8]},
-        "modes": {k: {kk: vv for kk, vv in v.items()} for k, v in res.items()},
+        "config": {"workload": "disc16k: central mass 1 + 16383 stars of 1e-7, a log-uniform [0.1, 1], "
+                               "8th-order modified Hermite, P(EC)^3, dt=2pi/2000, G=1, eps=0",
+                   "n_bodies": n, "order": 8, "n_iter": 3},
+        "roofline": dict(r["roofline"],
+                         kernel="force_kernel<K=3, FP64> + split reduction (one evaluation)",
+                         flops_per_interaction=FLOPS_PER_INTERACTION[8],
+                         algorithmic_bytes=(13 + 12) * 8 * n),
+        "fp64": {k: v for k, v in r.items() if k != "roofline"},
+        "mixed": dict(mx, dtype="f32 chain, f64 state/differences/cross-tile sums",
+                      vs_fp64={"energy_rel_change_diff": mx["energy_rel_change"] - r["energy_rel_change"],
+                               "max_ecc_vector_diff": de, "max_periapsis_diff_rad": dw,
+                               "bodies_compared": 256, "after_steps": args.steps + args.warmup}),
+        "mixed_over_fp64": mx["value"] / r["value"],
     }
-    mx = res["mixed"]
-    mx_ach = mx["flops_per_eval"] / (mx["eval_ms_avg"] / 1e3) / 1e12
-    out["modes"]["mixed"]["roofline"] = {"bound": "alu", "achieved": mx_ach, "peak": PEAK_TFLOPS["mixed"],
-                                         "unit": "TFLOP/s", "frac": mx_ach / PEAK_TFLOPS["mixed"]}
-    out["mixed_over_fp64"] = mx["value"] / r["value"]
+    if calib:
+        out["copy_calibration"] = calib
+    if not args.no_batched:
+        log("  batched ...")
+        out["batched"] = batched(args.batched_steps)
+        log("  batched: %s" % json.dumps({k: out["batched"][k] for k in ("fp64", "mixed")}))
     if not args.no_cpu_baseline:
         log("  cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

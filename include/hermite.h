@@ -184,18 +184,24 @@ hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const doubl
  * Launch-shape tuning for hermite_force_derivs.
  *   i_per_thread   1 or 2 i-particles per lane
  *   j_split        number of j-ranges summed by separate workgroups (0 = auto,
- *                  1..64; an upper bound: it is reduced to what the workspace
- *                  holds and to one range per 256 j)
+ *                  1..64; an upper bound: it is reduced to one range per 256 j
+ *                  and to what the workspace holds, which is 64 ranges while
+ *                  n * 64 <= 4 Mi and at least 4 at any n <= n_max)
  *   j_source       0: j-particles staged through LDS tiles by each workgroup;
  *                  1: j-particles packed once per evaluation into 128-byte
  *                  records and streamed through the scalar unit into SGPRs
+ *   wg_waves       4 or 16 wave64 per workgroup; 16 (scalar source and one
+ *                  i-particle per lane only): the waves share 64 i-particles
+ *                  and split the j-range among themselves, adding their sums
+ *                  through LDS, so a modest N needs no j_split
  * E_ARG for values outside these sets.  hermite_autotune times the supported
  * shapes on the given state (which must hold a valid path in s->pred),
  * keeps the fastest and returns it through the non-NULL out pointers.
  */
-hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source);
+hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source,
+                                  int32_t wg_waves);
 hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_per_thread, int32_t *j_split,
-                                int32_t *j_source);
+                                int32_t *j_source, int32_t *wg_waves);
 
 /* Message of the last failed call on ctx ("" if none; static string for NULL). */
 const char *hermite_last_error(const hermite_ctx *ctx);

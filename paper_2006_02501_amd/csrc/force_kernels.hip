@@ -2,12 +2,15 @@
 // derivatives (the hot loop of every P(EC)^n iteration).
 //
 // Layout on the chip: a workgroup is 4 wave64 (256 lanes).  Each lane keeps
-// IPT i-particles (their path x, v, a, adot and the running sums) in VGPRs.
+// IPT i-particles (their path x, v, a, adot and the running sums) in VGPRs;
+// in the LDS-tiled kernel the four waves share the same 64*IPT i-particles
+// and each takes a quarter of every j-tile, their sums being added through
+// LDS at the end (4x fewer split partials than one i-set per lane).
 // The workgroup walks its j-range in tiles of 256 j-particles; every tile is
 // read from HBM once, coalesced (consecutive lanes, consecutive j), into LDS
 // as one row per j (G m, then the path components), and every lane then
-// reads the rows as wave-wide broadcasts.  The j-range is split over
-// gridDim.y workgroups so that a modest N still fills 256 CUs; the split
+// reads the rows as wave-wide broadcasts.  The j-range is also split over
+// gridDim.y workgroups so that a modest N still fills 256 CUs; those split
 // partial sums are added in a fixed order by a second kernel (no atomics,
 // bitwise reproducible).
 //
@@ -28,17 +31,22 @@ struct Path {
 };
 
 constexpr int kFold = 32;   // mixed chain: j-particles per FP32 partial sum
+constexpr int kWave = 64;   // lanes per wavefront
+
+// i-particles per workgroup of W waves: 64*IPT when the waves share them
+// (and split the j-range), else 64*W*IPT.
+constexpr int64_t iblock_size(int w, bool share, int ipt) { return (int64_t)(share ? kWave : kWave * w) * ipt; }
 
 template <int K>
 constexpr int row_stride() { return ((1 + 3 * (K + 1)) + 1) & ~1; }
 
-template <int K, Chain CH, int IPT, bool DIAG>
+template <int K, Chain CH, int IPT, bool DIAG, int UNROLL = 2>
 __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const float *__restrict__ mtile, int cnt,
                                           int64_t j0, const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
                                           double eps2, double (&acc)[IPT][K + 1][3], float (&accf)[IPT][K + 1][3])
 {
     constexpr int RS = row_stride<K>();
-#pragma unroll 2
+#pragma unroll UNROLL
     for (int jj = 0; jj < cnt; ++jj) {
         const double *row = tile + jj * RS;
 #pragma unroll
@@ -94,17 +102,58 @@ __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const
     }
 }
 
-template <int K, Chain CH, int IPT>
-__global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
-                                                       double G, double eps2, int64_t j_chunk, int k_first,
-                                                       double *__restrict__ out)
+// Reduction of the W waves' partial sums through LDS, in wave order; wave 0
+// ends up with the workgroup's sum.  buf holds (W-1)*IPT*(K+1)*3*64 doubles.
+template <int K, int IPT, int W>
+__device__ __forceinline__ void reduce_waves(double *buf, int wave, int lane, double (&acc)[IPT][K + 1][3])
+{
+    constexpr int NV = IPT * (K + 1) * 3;
+    __syncthreads();
+    if (wave > 0) {
+        double *b = buf + (wave - 1) * NV * kWave;
+#pragma unroll
+        for (int q = 0; q < IPT; ++q)
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) b[((q * (K + 1) + k) * 3 + c) * kWave + lane] = acc[q][k][c];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 0; w < W - 1; ++w)
+#pragma unroll
+            for (int q = 0; q < IPT; ++q)
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[q][k][c] += buf[(w * NV + (q * (K + 1) + k) * 3 + c) * kWave + lane];
+    }
+}
+
+// A workgroup is W wave64.  SHARE: the W waves share one block of 64*IPT
+// i-particles and each takes its 64-row slice of every j-tile (their sums are
+// added through LDS at the end); otherwise every lane has its own i-particles.
+// A j-tile has 64*W rows, one loaded by each thread.
+template <int K, Chain CH, int IPT, int W, bool SHARE>
+__global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
+                                                          double G, double eps2, int64_t j_chunk, int k_first,
+                                                          double *__restrict__ out)
 {
     constexpr int RS = row_stride<K>();
-    __shared__ __align__(16) double tile[kTile * RS];
-    __shared__ float mtile[CH == Chain::Mixed ? kTile : 1];
+    constexpr int UNR = 2;
+    constexpr int TROWS = kWave * W;
+    constexpr int TILE_D = TROWS * RS;
+    constexpr int RED_D = SHARE ? (W - 1) * IPT * (K + 1) * 3 * kWave : 0;
+    __shared__ __align__(16) double smem[TILE_D > RED_D ? TILE_D : RED_D];
+    double *tile = smem;
+    __shared__ float mtile[CH == Chain::Mixed ? TROWS : 1];
     const int tid = threadIdx.x;
-    const int64_t ib0 = (int64_t)blockIdx.x * (kBlock * IPT);
-    const int64_t ib1 = min(n, ib0 + (int64_t)(kBlock * IPT));
+    const int wave = tid / kWave, lane = tid % kWave;
+    constexpr int ISTRIDE = SHARE ? kWave : kWave * W;
+    constexpr int IBLK = ISTRIDE * IPT;
+    const int64_t ib0 = (int64_t)blockIdx.x * IBLK;
+    const int64_t ib1 = min(n, ib0 + (int64_t)IBLK);
     const int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
     const int64_t jend = min(n, jbeg + j_chunk);
 
@@ -114,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *
     float accf[IPT][K + 1][3];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        ii[q] = ib0 + q * kBlock + tid;
+        ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
         const bool ok = ii[q] < n;
 #pragma unroll
         for (int k = 0; k <= K; ++k)
@@ -126,8 +175,8 @@ __global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *
             }
     }
 
-    for (int64_t j0 = jbeg; j0 < jend; j0 += kTile) {
-        const int cnt = (int)min((int64_t)kTile, jend - j0);
+    for (int64_t j0 = jbeg; j0 < jend; j0 += TROWS) {
+        const int cnt = (int)min((int64_t)TROWS, jend - j0);
         __syncthreads();
         if (tid < cnt) {
             const int64_t j = j0 + tid;
@@ -142,20 +191,25 @@ __global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *
         }
         __syncthreads();
         const bool diag = (j0 < ib1) && (ib0 < j0 + cnt);
+        // rows of this tile that this lane's wave handles
+        const int r0 = SHARE ? min(cnt, wave * kWave) : 0;
+        const int r1 = SHARE ? min(cnt, r0 + kWave) : cnt;
         if constexpr (CH != Chain::Mixed) {
-            if (diag)
-                tile_pass<K, CH, IPT, true>(tile, mtile, cnt, j0, ii, xi, eps2, acc, accf);
-            else
-                tile_pass<K, CH, IPT, false>(tile, mtile, cnt, j0, ii, xi, eps2, acc, accf);
+            if (r1 > r0) {
+                if (diag)
+                    tile_pass<K, CH, IPT, true, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc, accf);
+                else
+                    tile_pass<K, CH, IPT, false, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc, accf);
+            }
         } else {
             // FP32 partial sums over kFold j at a time, folded into FP64: bounds
             // the rounding that small terms suffer next to a dominant one.
-            for (int s0 = 0; s0 < cnt; s0 += kFold) {
-                const int cs = min(kFold, cnt - s0);
+            for (int s0 = r0; s0 < r1; s0 += kFold) {
+                const int cs = min(kFold, r1 - s0);
                 if (diag)
-                    tile_pass<K, CH, IPT, true>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, true, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
                 else
-                    tile_pass<K, CH, IPT, false>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, false, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
 #pragma unroll
                 for (int q = 0; q < IPT; ++q)
 #pragma unroll
@@ -169,6 +223,10 @@ __global__ __launch_bounds__(kBlock) void force_kernel(int64_t n, const double *
         }
     }
 
+    if constexpr (SHARE) {
+        reduce_waves<K, IPT, W>(smem, wave, lane, acc);
+        if (wave != 0) return;
+    }
     const int nv = K + 1 - k_first;
     double *o = out + (int64_t)blockIdx.y * nv * 3 * n;
 #pragma unroll
@@ -306,16 +364,30 @@ __device__ __forceinline__ void stream_folded(const double *__restrict__ jrec, i
     }
 }
 
-template <int K, Chain CH, int IPT>
-__global__ __launch_bounds__(kBlock) void force_stream_kernel(int64_t n, const double *__restrict__ jrec,
-                                                              Path<K> path, double eps2, int64_t j_chunk,
-                                                              double *__restrict__ out)
+// W waves per workgroup.  SHARE: they share 64*IPT i-particles and each
+// streams its own contiguous part of the workgroup's j-range (sums added
+// through LDS); otherwise they stream the same records for different i.
+template <int K, Chain CH, int IPT, int W, bool SHARE>
+__global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, const double *__restrict__ jrec,
+                                                                 Path<K> path, double eps2, int64_t j_chunk,
+                                                                 double *__restrict__ out)
 {
+    __shared__ double red[SHARE ? (W - 1) * IPT * (K + 1) * 3 * kWave : 1];
     const int tid = threadIdx.x;
-    const int64_t ib0 = (int64_t)blockIdx.x * (kBlock * IPT);
-    const int64_t ib1 = min(n, ib0 + (int64_t)(kBlock * IPT));
-    const int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
-    const int64_t jend = min(n, jbeg + j_chunk);
+    const int wave = tid / kWave, lane = tid % kWave;
+    constexpr int ISTRIDE = SHARE ? kWave : kWave * W;
+    constexpr int IBLK = ISTRIDE * IPT;
+    const int64_t ib0 = (int64_t)blockIdx.x * IBLK;
+    const int64_t ib1 = min(n, ib0 + (int64_t)IBLK);
+    int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
+    int64_t jend = min(n, jbeg + j_chunk);
+    if (SHARE) {
+        // this wave's contiguous part of the workgroup's j-range
+        const int64_t part = (max(jend - jbeg, (int64_t)0) + W - 1) / W;
+        const int64_t wb = jbeg + wave * part;
+        jend = min(jend, wb + part);
+        jbeg = min(wb, jend);
+    }
 
     int64_t ii[IPT];
     double xi[IPT][K + 1][3];
@@ -323,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void force_stream_kernel(int64_t n, const d
     float accf[IPT][K + 1][3];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        ii[q] = ib0 + q * kBlock + tid;
+        ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
         const bool ok = ii[q] < n;
 #pragma unroll
         for (int k = 0; k <= K; ++k)
@@ -341,6 +413,10 @@ __global__ __launch_bounds__(kBlock) void force_stream_kernel(int64_t n, const d
     stream_folded<K, CH, IPT, true>(jrec, d0, d1, ii, xi, eps2, acc, accf);
     stream_folded<K, CH, IPT, false>(jrec, d1, jend, ii, xi, eps2, acc, accf);
 
+    if constexpr (SHARE) {
+        reduce_waves<K, IPT, W>(red, wave, lane, acc);
+        if (wave != 0) return;
+    }
     double *o = out + (int64_t)blockIdx.y * (K + 1) * 3 * n;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
@@ -362,20 +438,20 @@ __global__ void reduce_splits_kernel(int64_t count, int nsplit, const double *__
     out[e] = s;
 }
 
-template <int K, Chain CH, int IPT>
-hipError_t launch_t(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+template <int K, Chain CH, int IPT, int W, bool SHARE>
+hipError_t launch_lds(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
 {
     Path<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
-    const int64_t iblocks = (a.n + kBlock * IPT - 1) / (kBlock * IPT);
-    dim3 grid((unsigned)iblocks, (unsigned)nsplit);
-    hipLaunchKernelGGL((force_kernel<K, CH, IPT>), grid, dim3(kBlock), 0, st, a.n, a.mass, path, a.G, a.eps2,
-                       j_chunk, a.k_first, dst);
+    const int64_t ib = iblock_size(W, SHARE, IPT);
+    dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
+    hipLaunchKernelGGL((force_kernel<K, CH, IPT, W, SHARE>), grid, dim3(kWave * W), 0, st, a.n, a.mass, path, a.G,
+                       a.eps2, j_chunk, a.k_first, dst);
     return hipGetLastError();
 }
 
-template <int K, Chain CH, int IPT>
-hipError_t launch_stream_t(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+template <int K, Chain CH, int IPT, int W, bool SHARE>
+hipError_t launch_stream(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
 {
     Path<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
@@ -383,73 +459,75 @@ hipError_t launch_stream_t(const ForceArgs &a, int nsplit, int64_t j_chunk, doub
                        a.mass, path, a.G, a.jrec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t iblocks = (a.n + kBlock * IPT - 1) / (kBlock * IPT);
-    dim3 grid((unsigned)iblocks, (unsigned)nsplit);
-    hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT>), grid, dim3(kBlock), 0, st, a.n, (const double *)a.jrec,
-                       path, a.eps2, j_chunk, dst);
+    const int64_t ib = iblock_size(W, SHARE, IPT);
+    dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
+    hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT, W, SHARE>), grid, dim3(kWave * W), 0, st, a.n,
+                       (const double *)a.jrec, path, a.eps2, j_chunk, dst);
     return hipGetLastError();
 }
 
-template <Chain CH>
-hipError_t dispatch_stream(const ForceArgs &a, int ipt, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+// Shapes: LDS source: 4 waves sharing an i-block; scalar source: 4 waves with
+// their own i (sharing the streamed records) or 16 waves sharing an i-block
+// (one i-particle per lane).
+template <int K, Chain CH>
+hipError_t dispatch_k(const ForceArgs &a, const LaunchShape &sh, int nsplit, int64_t j_chunk, double *dst,
+                      hipStream_t st)
 {
-    if (ipt == 1) {
-        switch (a.K) {
-            case 1: return launch_stream_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
-            case 2: return launch_stream_t<2, CH, 1>(a, nsplit, j_chunk, dst, st);
-            case 3: return launch_stream_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
-            default: return hipErrorInvalidValue;
-        }
+    const bool scalar = sh.jsource == JSource::Scalar;
+    if (sh.waves == 16) {
+        // 1024-thread workgroups: 128 VGPRs per lane, which the LDS-tiled
+        // kernel (its j-rows live in VGPRs) cannot meet without spilling.
+        if (sh.ipt != 1 || !scalar) return hipErrorInvalidValue;
+        return launch_stream<K, CH, 1, 16, true>(a, nsplit, j_chunk, dst, st);
     }
-    if (ipt == 2) {
-        switch (a.K) {
-            case 1: return launch_stream_t<1, CH, 2>(a, nsplit, j_chunk, dst, st);
-            case 2: return launch_stream_t<2, CH, 2>(a, nsplit, j_chunk, dst, st);
-            case 3: return launch_stream_t<3, CH, 2>(a, nsplit, j_chunk, dst, st);
-            default: return hipErrorInvalidValue;
-        }
-    }
+    if (sh.waves != 4) return hipErrorInvalidValue;
+    if (sh.ipt == 1)
+        return scalar ? launch_stream<K, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st)
+                      : launch_lds<K, CH, 1, 4, true>(a, nsplit, j_chunk, dst, st);
+    if (sh.ipt == 2)
+        return scalar ? launch_stream<K, CH, 2, 4, false>(a, nsplit, j_chunk, dst, st)
+                      : launch_lds<K, CH, 2, 4, true>(a, nsplit, j_chunk, dst, st);
     return hipErrorInvalidValue;
 }
 
 template <Chain CH>
-hipError_t dispatch(const ForceArgs &a, int ipt, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
+hipError_t dispatch(const ForceArgs &a, const LaunchShape &sh, int nsplit, int64_t j_chunk, double *dst,
+                    hipStream_t st)
 {
     if constexpr (CH == Chain::Generic) {
         switch (a.K) {
-            case 1: return launch_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
-            case 3: return launch_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
-            case 5: return launch_t<5, CH, 1>(a, nsplit, j_chunk, dst, st);
+            case 1: return launch_lds<1, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
+            case 3: return launch_lds<3, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
+            case 5: return launch_lds<5, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
             default: return hipErrorInvalidValue;
         }
     } else {
-        if (ipt == 1) {
-            switch (a.K) {
-                case 1: return launch_t<1, CH, 1>(a, nsplit, j_chunk, dst, st);
-                case 2: return launch_t<2, CH, 1>(a, nsplit, j_chunk, dst, st);
-                case 3: return launch_t<3, CH, 1>(a, nsplit, j_chunk, dst, st);
-                default: return hipErrorInvalidValue;
-            }
+        switch (a.K) {
+            case 1: return dispatch_k<1, CH>(a, sh, nsplit, j_chunk, dst, st);
+            case 2: return dispatch_k<2, CH>(a, sh, nsplit, j_chunk, dst, st);
+            case 3: return dispatch_k<3, CH>(a, sh, nsplit, j_chunk, dst, st);
+            default: return hipErrorInvalidValue;
         }
-        if (ipt == 2) {
-            switch (a.K) {
-                case 1: return launch_t<1, CH, 2>(a, nsplit, j_chunk, dst, st);
-                case 2: return launch_t<2, CH, 2>(a, nsplit, j_chunk, dst, st);
-                case 3: return launch_t<3, CH, 2>(a, nsplit, j_chunk, dst, st);
-                default: return hipErrorInvalidValue;
-            }
-        }
-        return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int auto_split(int64_t n, int ipt)
+int64_t shape_iblock(const LaunchShape &sh, bool generic)
+{
+    if (generic) return iblock_size(4, false, 1);
+    const bool share = sh.waves == 16 || sh.jsource == JSource::Lds;
+    return iblock_size(sh.waves, share, sh.ipt);
+}
+
+int auto_split(int64_t n, const LaunchShape &sh, bool generic)
 {
     if (n <= 0) return 1;
-    const int64_t iblocks = (n + kBlock * ipt - 1) / (kBlock * ipt);
-    const int64_t target = 1024;   // 4 workgroups (16 wave64) per CU on 256 CUs
+    const int64_t ib = shape_iblock(sh, generic);
+    const int64_t iblocks = (n + ib - 1) / ib;
+    // aim at 4096 resident waves (16 per CU) in one pass
+    const int64_t waves_per_wg = generic ? 4 : sh.waves;
+    const int64_t target = 4096 / waves_per_wg;
     int64_t s = (target + iblocks - 1) / iblocks;
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (s > tiles) s = tiles;
@@ -458,11 +536,14 @@ int auto_split(int64_t n, int ipt)
     return (int)s;
 }
 
-hipError_t launch_force(const ForceArgs &a, Chain chain, int ipt, int nsplit, hipStream_t st)
+hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, int nsplit, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
     const int nv = a.K + 1 - a.k_first;
     if (nv <= 0 || a.K >= kMaxPath) return hipErrorInvalidValue;
+    const bool generic = chain == Chain::Generic;
+    if (!generic && (a.k_first != 0 || a.K > 3)) return hipErrorInvalidValue;
+    if (!generic && sh.jsource == JSource::Scalar && !a.jrec) return hipErrorInvalidValue;
     const int64_t per_split = (int64_t)nv * 3 * a.n;
     if (nsplit < 1) nsplit = 1;
     if (nsplit > 1 && (int64_t)nsplit * per_split > a.partial_cap) {
@@ -473,19 +554,11 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, int ipt, int nsplit, hi
     j_chunk = (j_chunk + kTile - 1) / kTile * kTile;
     nsplit = (int)((a.n + j_chunk - 1) / j_chunk);
     double *dst = nsplit > 1 ? a.partial : a.out;
-    const bool stream = a.jsource == JSource::Scalar && chain != Chain::Generic && a.k_first == 0 && a.jrec &&
-                        a.K <= 3;
     hipError_t e;
     switch (chain) {
-        case Chain::Fp64:
-            e = stream ? dispatch_stream<Chain::Fp64>(a, ipt, nsplit, j_chunk, dst, st)
-                       : dispatch<Chain::Fp64>(a, ipt, nsplit, j_chunk, dst, st);
-            break;
-        case Chain::Mixed:
-            e = stream ? dispatch_stream<Chain::Mixed>(a, ipt, nsplit, j_chunk, dst, st)
-                       : dispatch<Chain::Mixed>(a, ipt, nsplit, j_chunk, dst, st);
-            break;
-        default: e = dispatch<Chain::Generic>(a, ipt, nsplit, j_chunk, dst, st); break;
+        case Chain::Fp64: e = dispatch<Chain::Fp64>(a, sh, nsplit, j_chunk, dst, st); break;
+        case Chain::Mixed: e = dispatch<Chain::Mixed>(a, sh, nsplit, j_chunk, dst, st); break;
+        default: e = dispatch<Chain::Generic>(a, sh, nsplit, j_chunk, dst, st); break;
     }
     if (e != hipSuccess || nsplit == 1) return e;
     const int64_t blocks = (per_split + 255) / 256;

@@ -26,18 +26,25 @@ struct ForceArgs {
     double *out;                  // [K+1-k_first][3][n]
     double *partial;              // split partial sums [nsplit][K+1-k_first][3][n]
     int64_t partial_cap;          // capacity of partial, in doubles
-    JSource jsource;              // j-particle source (Scalar needs jrec, K <= 3, k_first = 0)
-    double *jrec;                 // packed j-records [n][16] (Scalar source)
+    double *jrec;                 // packed j-records [n][16] (scalar source)
+};
+
+// Launch shape of the FP64 / mixed evaluation (the generic initialisation
+// chain always uses 4-wave workgroups with one i-particle per lane).
+struct LaunchShape {
+    int ipt;          // i-particles per lane: 1 or 2
+    int waves;        // waves per workgroup: 4 or 16 (16 with ipt = 1 only)
+    JSource jsource;  // LDS tiles or scalar stream
 };
 
 // Doubles per particle of the packed j-stream.
 constexpr int kJRecDoubles = 16;
 
-// Evaluates with the given chain, i-particles per lane and j-split count.
-hipError_t launch_force(const ForceArgs &a, Chain chain, int ipt, int nsplit, hipStream_t st);
+// Evaluates with the given chain, launch shape and j-split count.
+hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &shape, int nsplit, hipStream_t st);
 
 // j-split count the evaluation uses when the caller does not fix one.
-int auto_split(int64_t n, int ipt);
+int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 
 hipError_t launch_predict(int p, int64_t n, double dt, const double *pos, const double *vel,
                           const double *deriv, double *pred, hipStream_t st);

@@ -47,45 +47,54 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 
 // One pair, derivatives 0..K (K <= 3), relative path components given.
 // mr3 = G m_j w^(-3/2), rinv2 = 1/w.  Adds mr3 * (r, J', S', C') into acc.
+// The chain's coefficients are formed already negated (n1 = -3 alpha, ...),
+// so every vector update is a plain fused multiply-add onto a value that is
+// not needed afterwards: on gfx950 these take the two-operand accumulate
+// encoding (v_fmac), which issues at a higher rate than the three-operand form.
 template <int K, typename T>
 __device__ __forceinline__ void chain_accumulate(const T (&r)[3], const T (&v)[3], const T (&a)[3],
                                                  const T (&j)[3], T mr3, T rinv2, T (&acc)[K + 1][3])
 {
     static_assert(K >= 1 && K <= 3, "chain supports 1..3 derivatives");
-    const T rv = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+    const T rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
     const T alpha = rv * rinv2;
-    const T c1 = T(3) * alpha;
+    T vv = T(0), ra = T(0), va = T(0), rj = T(0);
+    if constexpr (K >= 2) {
+        vv = fma_t(v[2], v[2], fma_t(v[1], v[1], v[0] * v[0]));
+        ra = fma_t(r[2], a[2], fma_t(r[1], a[1], r[0] * a[0]));
+    }
+    if constexpr (K >= 3) {
+        va = fma_t(v[2], a[2], fma_t(v[1], a[1], v[0] * a[0]));
+        rj = fma_t(r[2], j[2], fma_t(r[1], j[1], r[0] * j[0]));
+    }
+    const T n1 = T(-3) * alpha;                  // -3 alpha
     T J[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         acc[0][c] = fma_t(mr3, r[c], acc[0][c]);
-        J[c] = fma_t(-c1, r[c], v[c]);
+        J[c] = fma_t(n1, r[c], v[c]);
         acc[1][c] = fma_t(mr3, J[c], acc[1][c]);
     }
     if constexpr (K >= 2) {
-        const T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-        const T ra = r[0] * a[0] + r[1] * a[1] + r[2] * a[2];
         const T alpha2 = alpha * alpha;
         const T beta = fma_t(vv + ra, rinv2, alpha2);
-        const T c2 = T(2) * c1;          // 6 alpha
-        const T c3 = T(3) * beta;
+        const T n2 = T(2) * n1;                  // -6 alpha
+        const T n3 = T(-3) * beta;               // -3 beta
         T S[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            S[c] = fma_t(-c3, r[c], fma_t(-c2, J[c], a[c]));
+            S[c] = fma_t(n3, r[c], fma_t(n2, J[c], a[c]));
             acc[2][c] = fma_t(mr3, S[c], acc[2][c]);
         }
         if constexpr (K >= 3) {
-            const T va = v[0] * a[0] + v[1] * a[1] + v[2] * a[2];
-            const T rj = r[0] * j[0] + r[1] * j[1] + r[2] * j[2];
-            const T gamma = fma_t(fma_t(T(3), va, rj), rinv2,
-                                          alpha * fma_t(T(-4), alpha2, c3));
-            const T c4 = T(3) * c1;      // 9 alpha
-            const T c5 = T(3) * c3;      // 9 beta
-            const T c6 = T(3) * gamma;
+            // gamma = (3 v.a + r.j)/w + alpha (3 beta - 4 alpha^2)
+            const T gamma = fma_t(fma_t(T(3), va, rj), rinv2, alpha * fma_t(T(-4), alpha2, T(-1) * n3));
+            const T n4 = T(3) * n1;              // -9 alpha
+            const T n5 = T(3) * n3;              // -9 beta
+            const T n6 = T(-3) * gamma;          // -3 gamma
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T C = fma_t(-c6, r[c], fma_t(-c5, J[c], fma_t(-c4, S[c], j[c])));
+                const T C = fma_t(n6, r[c], fma_t(n5, J[c], fma_t(n4, S[c], j[c])));
                 acc[3][c] = fma_t(mr3, C, acc[3][c]);
             }
         }

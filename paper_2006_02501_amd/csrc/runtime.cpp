@@ -28,6 +28,7 @@ struct hermite_ctx {
     int ipt = 1;
     int nsplit = 0;          // 0: automatic
     int jsource = 1;         // 0: LDS tiles, 1: scalar stream
+    int waves = 4;           // waves per workgroup: 4 or 16
     double *jrec = nullptr;  // packed j-records [n_max][kJRecDoubles]
     std::string err;
     // batched form
@@ -114,17 +115,18 @@ bool good_dt(double dt) { return std::isfinite(dt) && dt != 0.0; }
 
 int64_t partial_capacity(int64_t n_max, int p)
 {
-    // split partial sums of up to p+1 derivative blocks; enough for the automatic
-    // split at any n <= n_max (n * auto_split(n) is at most ~ 1024 * kBlock + n).
+    // Split partial sums of up to p+1 derivative blocks.  Enough for every
+    // split count the launch tuning may pick: up to 64 splits while
+    // n * splits stays below ~4 Mi, at least 4 splits at any n <= n_max.
+    if (n_max <= 0) return 0;
     const int64_t nv = p + 1;
-    int64_t ns = std::min<int64_t>(64, hermite::auto_split(n_max, 1));
-    int64_t elems = std::max<int64_t>(n_max * ns, (int64_t)1100 * hermite::kBlock);
-    if (n_max == 0) elems = 0;
-    return nv * 3 * elems;
+    int64_t ns = ((int64_t)4 << 20) / n_max;
+    ns = std::max<int64_t>(4, std::min<int64_t>(64, ns));
+    return nv * 3 * n_max * ns;
 }
 
 hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
-                         const double *const *path, double *out, int ipt, int nsplit, int jsource)
+                         const double *const *path, double *out, int ipt, int nsplit, int jsource, int waves)
 {
     ForceArgs a{};
     a.n = s->n;
@@ -137,10 +139,10 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
     a.out = out;
     a.partial = ctx->partial;
     a.partial_cap = ctx->partial_cap;
-    a.jsource = jsource == 1 ? hermite::JSource::Scalar : hermite::JSource::Lds;
     a.jrec = ctx->jrec;
-    if (nsplit <= 0) nsplit = hermite::auto_split(s->n, ipt);
-    HIP_TRY(ctx, hermite::launch_force(a, chain, ipt, nsplit, ctx->stream), "force kernel launch");
+    hermite::LaunchShape sh{ipt, waves, jsource == 1 ? hermite::JSource::Scalar : hermite::JSource::Lds};
+    if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
+    HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
     return HERMITE_OK;
 }
 
@@ -224,16 +226,22 @@ hermite_status hermite_set_stream(hermite_ctx *ctx, void *hip_stream)
     return HERMITE_OK;
 }
 
-hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source)
+hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_t j_split, int32_t j_source,
+                                  int32_t wg_waves)
 {
     if (!ctx) return HERMITE_E_ARG;
     if (i_per_thread != 1 && i_per_thread != 2)
         return fail(ctx, HERMITE_E_ARG, "hermite: i_per_thread must be 1 or 2");
     if (j_split < 0 || j_split > 64) return fail(ctx, HERMITE_E_ARG, "hermite: j_split must be in 0..64");
     if (j_source != 0 && j_source != 1) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0 or 1");
+    if (wg_waves != 4 && wg_waves != 16) return fail(ctx, HERMITE_E_ARG, "hermite: wg_waves must be 4 or 16");
+    if (wg_waves == 16 && (i_per_thread != 1 || j_source != 1))
+        return fail(ctx, HERMITE_E_ARG,
+                    "hermite: 16-wave workgroups take one i-particle per lane and the scalar j-source");
     ctx->ipt = i_per_thread;
     ctx->nsplit = j_split;
     ctx->jsource = j_source;
+    ctx->waves = wg_waves;
     return HERMITE_OK;
 }
 
@@ -248,17 +256,17 @@ hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s)
     if (s->n > 0) {
         // pass 1: a, adot from (x, v)
         const double *path[hermite::kMaxPath] = {s->pos, s->vel};
-        st = run_force(ctx, s, Chain::Generic, 1, 0, path, s->deriv, 1, 0, 0);
+        st = run_force(ctx, s, Chain::Generic, 1, 0, path, s->deriv, 1, 0, 0, 4);
         if (st != HERMITE_OK) return st;
         if (p >= 2) {   // pass 2: a^(2), a^(3) from (x, v, a, adot)
             const double *path2[hermite::kMaxPath] = {s->pos, s->vel, s->deriv, s->deriv + n3};
-            st = run_force(ctx, s, Chain::Generic, 3, 2, path2, s->deriv + 2 * n3, 1, 0, 0);
+            st = run_force(ctx, s, Chain::Generic, 3, 2, path2, s->deriv + 2 * n3, 1, 0, 0, 4);
             if (st != HERMITE_OK) return st;
         }
         if (p >= 3) {   // pass 3: a^(4), a^(5) from (x, v, a, ..., a^(3))
             const double *path3[hermite::kMaxPath] = {s->pos, s->vel, s->deriv, s->deriv + n3,
                                                       s->deriv + 2 * n3, s->deriv + 3 * n3};
-            st = run_force(ctx, s, Chain::Generic, 5, 4, path3, s->deriv + 4 * n3, 1, 0, 0);
+            st = run_force(ctx, s, Chain::Generic, 5, 4, path3, s->deriv + 4 * n3, 1, 0, 0, 4);
             if (st != HERMITE_OK) return st;
         }
     }
@@ -287,7 +295,7 @@ hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
     const double *path[hermite::kMaxPath] = {};
     for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
     const Chain ch = ctx->prm.precision == HERMITE_MIXED ? Chain::Mixed : Chain::Fp64;
-    return run_force(ctx, s, ch, p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource);
+    return run_force(ctx, s, ch, p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves);
 }
 
 hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter)
@@ -334,46 +342,52 @@ hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, doubl
 }
 
 hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_per_thread, int32_t *j_split,
-                                int32_t *j_source)
+                                int32_t *j_source, int32_t *wg_waves)
 {
     if (!ctx) return HERMITE_E_ARG;
     if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
     hermite_status st = check_state(ctx, s, false, true);
     if (st != HERMITE_OK) return st;
-    int best_ipt = 1, best_split = 0, best_src = 1;
+    struct Cand {
+        int ipt, waves, src;
+    };
+    const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {1, 16, 1}};
+    int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
     if (s->n > 0) {
         hipEvent_t e0, e1;
         HIP_TRY(ctx, hipEventCreate(&e0), "event create");
         HIP_TRY(ctx, hipEventCreate(&e1), "event create");
         float best = 1e30f;
-        for (int src = 0; src <= 1 && st == HERMITE_OK; ++src) {
-            for (int ipt = 1; ipt <= 2 && st == HERMITE_OK; ++ipt) {
-                const int base = hermite::auto_split(s->n, ipt);
-                std::vector<int> cands = {base};
-                for (int f : {2, 4}) {
-                    if (base * f <= 64) cands.push_back(base * f);
-                    if (base / f >= 1) cands.push_back(base / f);
-                }
-                std::sort(cands.begin(), cands.end());
-                cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
-                for (int ns : cands) {
-                    ctx->ipt = ipt;
-                    ctx->nsplit = ns;
-                    ctx->jsource = src;
-                    st = hermite_force_derivs(ctx, s);   // warm-up
-                    if (st != HERMITE_OK) break;
-                    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream), "event record");
-                    for (int r = 0; r < 3 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
-                    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream), "event record");
-                    HIP_TRY(ctx, hipEventSynchronize(e1), "event sync");
-                    float ms = 0.0f;
-                    HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
-                    if (st == HERMITE_OK && ms < best) {
-                        best = ms;
-                        best_ipt = ipt;
-                        best_split = ns;
-                        best_src = src;
-                    }
+        for (const Cand &cd : shapes) {
+            if (st != HERMITE_OK) break;
+            const hermite::LaunchShape sh{cd.ipt, cd.waves, cd.src ? hermite::JSource::Scalar : hermite::JSource::Lds};
+            const int base = hermite::auto_split(s->n, sh, false);
+            std::vector<int> cands = {base};
+            for (int f : {2, 4}) {
+                if (base * f <= 64) cands.push_back(base * f);
+                if (base / f >= 1) cands.push_back(base / f);
+            }
+            std::sort(cands.begin(), cands.end());
+            cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+            for (int ns : cands) {
+                ctx->ipt = cd.ipt;
+                ctx->waves = cd.waves;
+                ctx->jsource = cd.src;
+                ctx->nsplit = ns;
+                st = hermite_force_derivs(ctx, s);   // warm-up
+                if (st != HERMITE_OK) break;
+                HIP_TRY(ctx, hipEventRecord(e0, ctx->stream), "event record");
+                for (int r = 0; r < 3 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
+                HIP_TRY(ctx, hipEventRecord(e1, ctx->stream), "event record");
+                HIP_TRY(ctx, hipEventSynchronize(e1), "event sync");
+                float ms = 0.0f;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
+                if (st == HERMITE_OK && ms < best) {
+                    best = ms;
+                    best_ipt = cd.ipt;
+                    best_waves = cd.waves;
+                    best_split = ns;
+                    best_src = cd.src;
                 }
             }
         }
@@ -384,9 +398,11 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
     ctx->ipt = best_ipt;
     ctx->nsplit = best_split;
     ctx->jsource = best_src;
+    ctx->waves = best_waves;
     if (i_per_thread) *i_per_thread = best_ipt;
     if (j_split) *j_split = best_split;
     if (j_source) *j_source = best_src;
+    if (wg_waves) *wg_waves = best_waves;
     return HERMITE_OK;
 }
 

@@ -56,9 +56,10 @@ _SIGS = {
                                             _P, ctypes.POINTER(_P)]),
     "hermite_batch_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
     "hermite_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]),
-    "hermite_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hermite_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hermite_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(ctypes.c_int32),
-                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "hermite_last_error": (ctypes.c_char_p, [_P]),
     "hermite_version": (ctypes.c_char_p, []),
 }
@@ -195,15 +196,18 @@ class Hermite:
         _check(self.ctx, self.lib.hermite_potential(self.ctx, ctypes.byref(st.c), ctypes.c_void_p(phi.data_ptr())))
         return phi
 
-    def set_launch(self, i_per_thread, j_split, j_source=1):
-        """j_source: 0 = LDS tiles, 1 = scalar stream (SGPR operands)."""
-        _check(self.ctx, self.lib.hermite_set_launch(self.ctx, int(i_per_thread), int(j_split), int(j_source)))
+    def set_launch(self, i_per_thread, j_split, j_source=1, wg_waves=4):
+        """j_source: 0 = LDS tiles, 1 = scalar stream (SGPR operands);
+        wg_waves: 4 or 16 wave64 per workgroup."""
+        _check(self.ctx, self.lib.hermite_set_launch(self.ctx, int(i_per_thread), int(j_split), int(j_source),
+                                                     int(wg_waves)))
 
     def autotune(self, st):
-        ipt, js, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """Times the supported launch shapes; returns (i_per_thread, j_split, j_source, wg_waves)."""
+        ipt, js, src, wv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self.ctx, self.lib.hermite_autotune(self.ctx, ctypes.byref(st.c), ctypes.byref(ipt), ctypes.byref(js),
-                                                   ctypes.byref(src)))
-        return ipt.value, js.value, src.value
+                                                   ctypes.byref(src), ctypes.byref(wv)))
+        return ipt.value, js.value, src.value, wv.value
 
 
 class BatchHermite:

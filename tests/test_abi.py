@@ -70,7 +70,7 @@ def test_null_context_calls():
     assert lib.hermite_correct(None, ctypes.byref(s), 0.1, 1) == -1
     assert lib.hermite_step(None, ctypes.byref(s), 0.1, 3) == -1
     assert lib.hermite_batch_run(None, ctypes.byref(s), None, 1, 1) == -1
-    assert lib.hermite_set_launch(None, 1, 1, 0) == -1
+    assert lib.hermite_set_launch(None, 1, 1, 0, 4) == -1
     assert lib.hermite_destroy(None) == 0
     assert lib.hermite_last_error(None)
     assert b"gfx950" in lib.hermite_version()
