@@ -34,7 +34,30 @@ KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_025
 # HBM bytes per evaluation launch (force kernel + split reduction), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {
+    "fp64": {
+        "sources_sha256": "e29c04997a6fa1945ce792fdac9eda0ae96a9b90742dba3618996c44c080c943",
+        "launch": {
+            "i_per_thread": 2,
+            "j_split": 4,
+            "j_source": "lds",
+            "wg_waves": 4
+        },
+        "fetch_bytes": 20772416,
+        "write_bytes": 7785677
+    },
+    "mixed": {
+        "sources_sha256": "e29c04997a6fa1945ce792fdac9eda0ae96a9b90742dba3618996c44c080c943",
+        "launch": {
+            "i_per_thread": 1,
+            "j_split": 64,
+            "j_source": "scalar",
+            "wg_waves": 4
+        },
+        "fetch_bytes": 137595141,
+        "write_bytes": 104333312
+    }
+}
 # MI355X published vector peaks: 256 CUs x 4 SIMD16 x 2 flops (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s FP64; FP32 twice that (157.3) with packed-FP32 issue.
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
@@ -179,7 +202,7 @@ def cpu_baseline(w, target_s=12.0):
                        % (reps, m_i, n, total))
 
 
-def batched(steps, baseline_systems=64, baseline_steps=10):
+def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
     """4096 systems of 3..64 bodies, 8th order, P(EC)^3, per-system dt, in one
     persistent graph-captured launch; against hermite_step on each system."""
     import torch
@@ -210,6 +233,8 @@ def batched(steps, baseline_systems=64, baseline_steps=10):
         ms = e0.elapsed_time(e1)
         bh.close()
         out[prec] = {"ms": ms, "interactions_per_s": steps * n_iter * inter_eval / (ms / 1e3)}
+    if not per_system:
+        return out
     # one launch sequence per system (hermite_step), a sample, extrapolated
     pick = np.linspace(0, len(sizes) - 1, baseline_systems).astype(int)
     t_total = 0.0
@@ -260,6 +285,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-per-system", action="store_true",
+                    help="skip the one-launch-per-system comparison of the batched workload")
     ap.add_argument("--launch", default=None,
                     help="fixed launch shapes instead of autotuning, e.g. 'fp64=2,16,0,4;mixed=1,1,1,16' "
                          "(i_per_thread, j_split, j_source, wg_waves)")
@@ -320,7 +347,7 @@ def main():
         out["copy_calibration"] = calib
     if not args.no_batched:
         log("  batched ...")
-        out["batched"] = batched(args.batched_steps)
+        out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)
         log("  batched: %s" % json.dumps({k: out["batched"][k] for k in ("fp64", "mixed")}))
     if not args.no_cpu_baseline:
         log("  cpu baseline (oracle) ...")

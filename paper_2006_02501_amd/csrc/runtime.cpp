@@ -351,13 +351,18 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
     struct Cand {
         int ipt, waves, src;
     };
+    struct Timed {
+        Cand c;
+        int split;
+        float ms;
+    };
     const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {1, 16, 1}};
     int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
     if (s->n > 0) {
         hipEvent_t e0, e1;
         HIP_TRY(ctx, hipEventCreate(&e0), "event create");
         HIP_TRY(ctx, hipEventCreate(&e1), "event create");
-        float best = 1e30f;
+        std::vector<Timed> timed;
         for (const Cand &cd : shapes) {
             if (st != HERMITE_OK) break;
             const hermite::LaunchShape sh{cd.ipt, cd.waves, cd.src ? hermite::JSource::Scalar : hermite::JSource::Lds};
@@ -377,23 +382,32 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
                 st = hermite_force_derivs(ctx, s);   // warm-up
                 if (st != HERMITE_OK) break;
                 HIP_TRY(ctx, hipEventRecord(e0, ctx->stream), "event record");
-                for (int r = 0; r < 3 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
+                for (int r = 0; r < 5 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
                 HIP_TRY(ctx, hipEventRecord(e1, ctx->stream), "event record");
                 HIP_TRY(ctx, hipEventSynchronize(e1), "event sync");
                 float ms = 0.0f;
                 HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
-                if (st == HERMITE_OK && ms < best) {
-                    best = ms;
-                    best_ipt = cd.ipt;
-                    best_waves = cd.waves;
-                    best_split = ns;
-                    best_src = cd.src;
-                }
+                if (st == HERMITE_OK) timed.push_back({cd, ns, ms});
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st != HERMITE_OK) return st;
+        // Fastest shape; among those within 2 % of it, the one that writes the
+        // fewest split partial sums (then the earliest in the list above).
+        float best = 1e30f;
+        for (const Timed &t : timed) best = std::min(best, t.ms);
+        const Timed *pick = nullptr;
+        for (const Timed &t : timed) {
+            if (t.ms > 1.02f * best) continue;
+            if (!pick || t.split < pick->split) pick = &t;
+        }
+        if (pick) {
+            best_ipt = pick->c.ipt;
+            best_waves = pick->c.waves;
+            best_src = pick->c.src;
+            best_split = pick->split;
+        }
     }
     ctx->ipt = best_ipt;
     ctx->nsplit = best_split;
