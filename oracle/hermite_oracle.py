@@ -31,6 +31,8 @@ What each function follows (section / equation of the paper):
                            from the Hermite interpolant through a^(0..p) at both
                            ends, solved numerically (confluent Vandermonde).
 * ``step``                 Sec. 2 end / Sec. 3: P(EC)^n iteration.
+* ``step_criterion``,      Sec. 3.3, Eq. 25: the minimum two-body time scale
+  ``step_symmetric``       and the implicit time-symmetric step (reading R21).
 * ``energy``, ``kepler_elements``  Sec. 3.1 diagnostics; eccentricity vector of
                            Appendix A (first equation).
 
@@ -42,6 +44,10 @@ Readings where the paper is silent (frozen identically in the HIP path):
   R3  P(EC)^n iteration k >= 2 evaluates at the corrected (x1, v1) with the
       relative a, adot taken from iteration k-1's evaluation.
   R6  the self term is excluded by index, never by distance.
+  R21 variable step (Sec. 3.3): H_- at the start of the step, the prediction
+      with dt = H_-; iteration k corrects with dt = (H_- + H_+)/2, H_+ taken
+      at iteration k's evaluation point (the latest estimate of the end of
+      the step).  Converged iterations give the time-symmetric step.
 
 Parity pins for every function are in ``tests/test_oracle_*.py``.
 """
@@ -164,6 +170,8 @@ def _load():
         lib.oracle_potential.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int64, ip, dp]
         lib.oracle_potential.restype = ctypes.c_int
+        lib.oracle_max_pair_rate.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double, dp]
+        lib.oracle_max_pair_rate.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -238,6 +246,21 @@ def potential_per_particle(mass, x, G=1.0, eps2=0.0, i_list=None):
     if rc != 0:
         raise ValueError("oracle_potential: bad arguments (%d)" % rc)
     return phi
+
+
+def step_criterion(mass, x, eta, G=1.0, eps2=0.0):
+    """Eq. 25: H = eta min_{i != j} ((r_ij^2 + eps^2)^(3/2) / (G (m_i + m_j)))^(1/2)
+    (the minimum two-body Keplerian period scale; G = 1 in the paper)."""
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(3, n))
+    q = ctypes.c_double()
+    rc = _load().oracle_max_pair_rate(n, _dptr(mass), _dptr(x), float(G), float(eps2), ctypes.byref(q))
+    if rc != 0:
+        raise ValueError("oracle_max_pair_rate: bad arguments")
+    if q.value <= 0.0:
+        raise ValueError("step criterion needs at least two bodies")
+    return eta / np.sqrt(q.value)
 
 
 def energy(mass, x, v, G=1.0, eps2=0.0):
@@ -435,6 +458,34 @@ def step(st, dt, n_iter, corrector="modified", G=1.0, eps2=0.0, return_iterates=
     st.derivs = list(a1) + higher
     st.t += dt
     return iterates if return_iterates else st
+
+
+def step_symmetric(st, eta, n_iter, corrector="modified", G=1.0, eps2=0.0, direction=1.0):
+    """One P(EC)^n step with the implicit time-symmetric step of Sec. 3.3
+    (reading R21).  H_- = H(x0) at the start; the prediction uses dt = H_-;
+    every evaluation also gives H at its evaluation point (the current
+    estimate of the end of the step, H_+), and that iteration's correction uses
+    dt = (H_- + H_+)/2.  ``direction`` = -1 integrates backwards.
+    Returns the dt of the last correction (the step actually taken)."""
+    if n_iter < 1:
+        raise ValueError("n_iter must be >= 1")
+    p = st.p
+    a0 = st.derivs[: p + 1]
+    Hm = step_criterion(st.mass, st.x, eta, G, eps2)
+    dt = direction * Hm
+    path = predict(p, dt, st.x, st.v, st.derivs)
+    for _ in range(n_iter):
+        out = pair_derivs(st.mass, path, K=p, G=G, eps2=eps2)
+        a1 = [out[k] for k in range(p + 1)]
+        Hp = step_criterion(st.mass, path[0], eta, G, eps2)
+        dt = direction * 0.5 * (Hm + Hp)
+        x1, v1 = correct(p, dt, st.x, st.v, a0, a1, corrector)
+        path = [x1, v1] + a1[: p - 1]
+    higher = interpolate_higher(p, dt, a0, a1)
+    st.x, st.v = x1, v1
+    st.derivs = list(a1) + higher
+    st.t += dt
+    return dt
 
 
 def run(st, dt, n_steps, n_iter, corrector="modified", G=1.0, eps2=0.0, callback=None):

@@ -184,3 +184,27 @@ int oracle_num_threads(void)
     }
     return nt;
 }
+
+/*
+ * Largest pair "rate" of the time-step criterion (Sec. 3.3, Eq. 25):
+ *   q = max_{i != j} G (m_i + m_j) / (r_ij^2 + eps^2)^(3/2),
+ * so that H = eta * q^(-1/2) = eta * min_{i != j} ((r^2+eps^2)^(3/2) / (G (m_i+m_j)))^(1/2).
+ * x is [3][n].  Returns 0 (with *qmax = 0 for n < 2), -1 on bad arguments.
+ */
+int oracle_max_pair_rate(int64_t n, const double *mass, const double *x, double G, double eps2, double *qmax)
+{
+    if (n < 0 || eps2 < 0.0 || !mass || !x || !qmax) return -1;
+    double best = 0.0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(max : best)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            const double w = dx * dx + dy * dy + dz * dz + eps2;
+            const double q = G * (mass[i] + mass[j]) / (w * sqrt(w));
+            if (q > best) best = q;
+        }
+    }
+    *qmax = best;
+    return 0;
+}

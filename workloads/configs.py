@@ -169,10 +169,22 @@ def large_disc(n=1048576):
                 steps=1, G=1.0, eps2=0.0)
 
 
+def disc100(n_bodies=100):
+    """The paper's N-body test (Sec. 3.3, Table 1): 100 bodies of 1e-5 around a
+    central mass 1, semi-major axes evenly log-spaced in [0.1, 10], e ~
+    Rayleigh(0.06) and i ~ Rayleigh(0.12) (sigma_i = 2 sigma_e = 0.12), angles
+    uniform; eps = 1e-6, t_end = 100 pi.  Seeded: no seed is given."""
+    rng = _rng(5)
+    a = np.geomspace(0.1, 10.0, n_bodies)
+    mass, x, v = _disc(rng, n_bodies + 1, 1.0, 1e-5, a, 0.06, 0.12)
+    return dict(name="disc100", mass=mass, x=x, v=v, order=8, eps2=1e-12, t_end=100 * np.pi, G=1.0)
+
+
 CONFIGS = {
     "ring64": ring64,
     "disc16k": disc16k,
     "plummer_cluster": plummer_cluster,
     "batch_systems": batch_systems,
     "large_disc": large_disc,
+    "disc100": disc100,
 }
