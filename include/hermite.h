@@ -155,6 +155,34 @@ hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, in
  * the last correction with last_iter = 1.  E_ARG if n_iter < 1. */
 hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32_t n_iter);
 
+/*
+ * Variable, time-symmetric step (Sec. 3.3, Eq. 25).  The criterion is
+ *   H(x) = eta min_{i != j} ((r_ij^2 + eps^2)^(3/2) / (G (m_i + m_j)))^(1/2),
+ * the shortest two-body Kepler time scale over all pairs, times eta.
+ *
+ * hermite_step_criterion: H at s->pos into the host double *h (synchronises).
+ * E_ARG if n < 2, eta is not finite and > 0, or h is NULL; E_NONFINITE if H
+ * is not finite and positive (no pair with G (m_i + m_j) > 0, coincident
+ * bodies without softening, non-finite positions).
+ *
+ * hermite_step_symmetric: one P(EC)^n step whose length is chosen implicitly
+ * as the iteration proceeds: H_- = H(x0) at the start, the prediction with
+ * dt = direction * H_-, and the correction of iteration k with
+ *   dt_k = direction * (H_- + H_+,k) / 2,
+ * H_+,k = H at iteration k's evaluation point (the predicted x, then the
+ * previous iteration's corrected x), so that converged iterations give a step
+ * that is the same taken forwards or backwards.  The step length stays on the
+ * device between launches; at the end it is copied back (synchronises),
+ * added to s->t and stored in *dt_taken (host, may be NULL).
+ * direction is +1 (forwards) or -1 (backwards).  E_ARG for n < 2, n_iter < 1,
+ * eta not finite and > 0, other directions; E_STATE before init;
+ * E_NONFINITE when H is undefined at any point of the step, in which case
+ * pos, vel, deriv and t are left unchanged (pred and eval are scratch).
+ */
+hermite_status hermite_step_criterion(hermite_ctx *ctx, const hermite_state *s, double eta, double *h);
+hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double eta, int32_t n_iter,
+                                      double direction, double *dt_taken);
+
 /* Energy diagnostic (Sec. 3.1): phi[i] = -sum_{j != i} G m_j (r_ij^2+eps^2)^(-1/2)
  * at s->pos, FP64, written to the device array phi[n]. */
 hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, double *phi);

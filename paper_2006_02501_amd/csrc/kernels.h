@@ -46,11 +46,22 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &shap
 // j-split count the evaluation uses when the caller does not fix one.
 int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 
-hipError_t launch_predict(int p, int64_t n, double dt, const double *pos, const double *vel,
+// Predictor and corrector take dt from dt_dev[0] when dt_dev is not null.
+hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, const double *pos, const double *vel,
                           const double *deriv, double *pred, hipStream_t st);
 
-hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, double *pos, double *vel,
-                          double *deriv, const double *eval, double *pred, hipStream_t st);
+hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
+                          double *vel, double *deriv, const double *eval, double *pred, hipStream_t st);
+
+// Time-step criterion (Sec. 3.3): number of workgroup maxima the rate pass
+// writes for n particles (and its j-split).
+int qmax_partials(int64_t n, int *nsplit, int64_t *j_chunk);
+
+// H = eta q^(-1/2) at x ([3][n], n >= 2) into vs (device double[4]):
+// mode 0: vs[0] = H, vs[1] = dir H; mode 1: vs[2] = H, vs[1] = dir (vs[0] + H)/2;
+// vs[3] = 1 (and vs[1] = 0) once H is not finite and positive.
+hipError_t launch_timestep(int64_t n, const double *mass, const double *x, double G, double eps2, double eta,
+                           double dir, int mode, double *qpart, int64_t qpart_cap, double *vs, hipStream_t st);
 
 hipError_t launch_potential(int64_t n, const double *mass, const double *pos, double G, double eps2,
                             double *phi, hipStream_t st);

@@ -30,6 +30,12 @@ struct hermite_ctx {
     int jsource = 1;         // 0: LDS tiles, 1: scalar stream
     int waves = 4;           // waves per workgroup: 4 or 16
     double *jrec = nullptr;  // packed j-records [n_max][kJRecDoubles]
+    // variable step: workgroup maxima of the pair rate, the device step
+    // record (H_-, dt, H_+, failed) and its pinned host copy
+    double *qpart = nullptr;
+    int64_t qpart_cap = 0;
+    double *vs = nullptr;
+    double *host_vs = nullptr;
     std::string err;
     // batched form
     bool batch = false;
@@ -158,6 +164,17 @@ hermite_status check_finite(hermite_ctx *ctx, const double *const *arrays, const
     return HERMITE_OK;
 }
 
+hermite_status alloc_timestep(hermite_ctx *ctx)
+{
+    // the rate pass writes at most ceil(n/256) + 2048 workgroup maxima
+    ctx->qpart_cap = (ctx->n_max + 255) / 256 + 2049;
+    if (hipMalloc((void **)&ctx->qpart, ctx->qpart_cap * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
+    if (hipMalloc((void **)&ctx->vs, 4 * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
+    if (hipHostMalloc((void **)&ctx->host_vs, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return HERMITE_E_ALLOC;
+    return HERMITE_OK;
+}
+
 void free_ctx(hermite_ctx *ctx)
 {
     if (!ctx) return;
@@ -171,6 +188,9 @@ void free_ctx(hermite_ctx *ctx)
     if (ctx->d_offsets) (void)hipFree(ctx->d_offsets);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     if (ctx->jrec) (void)hipFree(ctx->jrec);
+    if (ctx->qpart) (void)hipFree(ctx->qpart);
+    if (ctx->vs) (void)hipFree(ctx->vs);
+    if (ctx->host_vs) (void)hipHostFree(ctx->host_vs);
     delete ctx;
 }
 
@@ -206,6 +226,10 @@ hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hi
     }
     if (n_max > 0 &&
         hipMalloc((void **)&ctx->jrec, (size_t)n_max * hermite::kJRecDoubles * sizeof(double)) != hipSuccess) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    if (alloc_timestep(ctx) != HERMITE_OK) {
         free_ctx(ctx);
         return HERMITE_E_ALLOC;
     }
@@ -280,7 +304,7 @@ hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt)
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
-    HIP_TRY(ctx, hermite::launch_predict(ctx->p, s->n, dt, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
+    HIP_TRY(ctx, hermite::launch_predict(ctx->p, s->n, dt, nullptr, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
             "predict launch");
     return HERMITE_OK;
 }
@@ -304,7 +328,7 @@ hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, in
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
-    HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, s->pos, s->vel,
+    HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, nullptr, s->pos, s->vel,
                                          s->deriv, s->eval, s->pred, ctx->stream),
             "correct launch");
     if (last_iter) s->t += dt;
@@ -327,6 +351,75 @@ hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32
     if (st != HERMITE_OK || !ctx->prm.check_finite || s->n == 0) return st;
     const double *arrs[3] = {s->pos, s->vel, s->deriv};
     const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
+    return check_finite(ctx, arrs, cnt, 3);
+}
+
+hermite_status hermite_step_criterion(hermite_ctx *ctx, const hermite_state *s, double eta, double *h)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    hermite_status st = check_state(ctx, s, false, false);
+    if (st != HERMITE_OK) return st;
+    if (!h) return fail(ctx, HERMITE_E_ARG, "hermite: h is NULL");
+    if (!std::isfinite(eta) || !(eta > 0.0)) return fail(ctx, HERMITE_E_ARG, "hermite: eta must be finite and > 0");
+    if (s->n < 2) return fail(ctx, HERMITE_E_ARG, "hermite: the step criterion needs at least two particles");
+    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, 1.0, 0, ctx->qpart,
+                                          ctx->qpart_cap, ctx->vs, ctx->stream),
+            "step criterion launch");
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+            "step criterion copy");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "step criterion sync");
+    *h = ctx->host_vs[0];
+    if (ctx->host_vs[3] != 0.0)
+        return fail(ctx, HERMITE_E_NONFINITE,
+                    "hermite: step criterion not finite and positive (no pair with G (m_i + m_j) > 0, "
+                    "coincident bodies without softening, or non-finite positions)");
+    return HERMITE_OK;
+}
+
+hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double eta, int32_t n_iter,
+                                      double direction, double *dt_taken)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
+    if (!std::isfinite(eta) || !(eta > 0.0)) return fail(ctx, HERMITE_E_ARG, "hermite: eta must be finite and > 0");
+    if (direction != 1.0 && direction != -1.0) return fail(ctx, HERMITE_E_ARG, "hermite: direction must be +1 or -1");
+    hermite_status st = check_state(ctx, s, true, true);
+    if (st != HERMITE_OK) return st;
+    if (s->n < 2) return fail(ctx, HERMITE_E_ARG, "hermite: the step criterion needs at least two particles");
+    const int p = ctx->p;
+    const double *dtp = ctx->vs + 1;
+    // H_- at the start, prediction with dt = s H_-
+    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, direction, 0,
+                                          ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
+            "step criterion launch");
+    HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, dtp, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
+            "predict launch");
+    for (int it = 0; it < n_iter; ++it) {
+        st = hermite_force_derivs(ctx, s);
+        if (st != HERMITE_OK) return st;
+        // H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
+        HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pred, ctx->prm.G, ctx->prm.eps2, eta, direction, 1,
+                                              ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
+                "step criterion launch");
+        HIP_TRY(ctx, hermite::launch_correct(p, ctx->prm.corrector, it == n_iter - 1 ? 1 : 0, s->n, 0.0, dtp, s->pos,
+                                             s->vel, s->deriv, s->eval, s->pred, ctx->stream),
+                "correct launch");
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+            "step length copy");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "step length sync");
+    if (ctx->host_vs[3] != 0.0)
+        return fail(ctx, HERMITE_E_NONFINITE,
+                    "hermite: step criterion not finite and positive (no pair with G (m_i + m_j) > 0, "
+                    "coincident bodies without softening, or non-finite positions); state unchanged");
+    const double dt = ctx->host_vs[1];
+    s->t += dt;
+    if (dt_taken) *dt_taken = dt;
+    if (!ctx->prm.check_finite) return HERMITE_OK;
+    const double *arrs[3] = {s->pos, s->vel, s->deriv};
+    const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * p * 3 * s->n};
     return check_finite(ctx, arrs, cnt, 3);
 }
 

@@ -21,14 +21,19 @@ __device__ constexpr double kInv[9] = {0.0, 1.0, 1.0 / 2.0, 1.0 / 3.0, 1.0 / 4.0
 //   xp = sum_{k<=2P+1} x^(k) dt^k/k!,  vp = sum_{k<=2P} x^(k+1) dt^k/k!,
 //   ap = sum_{k<=2P-1} a^(k) dt^k/k!,  jp = sum_{k<=2P-2} a^(k+1) dt^k/k!.
 // Evaluated in Horner form, s = c_M; s = c_k + s dt/(k+1).
+// dt comes from dt_dev[0] when dt_dev is not null (a step length formed on
+// the device, the variable step of Sec. 3.3).
 template <int P>
-__global__ __launch_bounds__(kStepBlock) void predict_kernel(int64_t n3, double dt, const double *__restrict__ pos,
+__global__ __launch_bounds__(kStepBlock) void predict_kernel(int64_t n3, double dt_host,
+                                                             const double *__restrict__ dt_dev,
+                                                             const double *__restrict__ pos,
                                                              const double *__restrict__ vel,
                                                              const double *__restrict__ deriv,
                                                              double *__restrict__ pred)
 {
     const int64_t e = (int64_t)blockIdx.x * kStepBlock + threadIdx.x;
     if (e >= n3) return;
+    const double dt = dt_dev ? dt_dev[0] : dt_host;
     double xs[2 * P + 2];
     xs[0] = pos[e];
     xs[1] = vel[e];
@@ -49,15 +54,20 @@ __global__ __launch_bounds__(kStepBlock) void predict_kernel(int64_t n3, double 
 
 // Modified corrector, velocity first then position (Eq. 6-8, Eq. 22-24),
 // for one element; on the last iteration also the interpolated
-// a^(P+1..2P-1) at the end of the step.
+// a^(P+1..2P-1) at the end of the step.  dt as in the predictor; a device
+// dt of exactly 0 marks a step whose length could not be formed, and then
+// nothing is written.
 template <int P, int CORR>
-__global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double dt, int last, double *__restrict__ pos,
+__global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double dt_host,
+                                                             const double *__restrict__ dt_dev, int last,
+                                                             double *__restrict__ pos,
                                                              double *__restrict__ vel, double *__restrict__ deriv,
                                                              const double *__restrict__ eval,
                                                              double *__restrict__ pred)
 {
     const int64_t e = (int64_t)blockIdx.x * kStepBlock + threadIdx.x;
-    if (e >= n3) return;
+    const double dt = dt_dev ? dt_dev[0] : dt_host;
+    if (e >= n3 || dt == 0.0) return;
     double a0[P + 1], a1[P + 1];
 #pragma unroll
     for (int k = 0; k <= P; ++k) {
@@ -160,14 +170,14 @@ __global__ __launch_bounds__(kStepBlock) void check_finite_kernel(const double *
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kStepBlock - 1) / kStepBlock); }
 
 template <int P>
-hipError_t correct_p(int corrector, int last, int64_t n3, double dt, double *pos, double *vel, double *deriv,
-                     const double *eval, double *pred, hipStream_t st)
+hipError_t correct_p(int corrector, int last, int64_t n3, double dt, const double *dt_dev, double *pos, double *vel,
+                     double *deriv, const double *eval, double *pred, hipStream_t st)
 {
     const dim3 g(blocks_for(n3)), b(kStepBlock);
     switch (corrector) {
-        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, last, pos, vel, deriv, eval, pred); break;
-        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, last, pos, vel, deriv, eval, pred); break;
-        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, last, pos, vel, deriv, eval, pred); break;
+        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
+        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
+        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -175,30 +185,30 @@ hipError_t correct_p(int corrector, int last, int64_t n3, double dt, double *pos
 
 }  // namespace
 
-hipError_t launch_predict(int p, int64_t n, double dt, const double *pos, const double *vel, const double *deriv,
-                          double *pred, hipStream_t st)
+hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, const double *pos, const double *vel,
+                          const double *deriv, double *pred, hipStream_t st)
 {
     const int64_t n3 = 3 * n;
     if (n3 <= 0) return hipSuccess;
     const dim3 g(blocks_for(n3)), b(kStepBlock);
     switch (p) {
-        case 1: hipLaunchKernelGGL(predict_kernel<1>, g, b, 0, st, n3, dt, pos, vel, deriv, pred); break;
-        case 2: hipLaunchKernelGGL(predict_kernel<2>, g, b, 0, st, n3, dt, pos, vel, deriv, pred); break;
-        case 3: hipLaunchKernelGGL(predict_kernel<3>, g, b, 0, st, n3, dt, pos, vel, deriv, pred); break;
+        case 1: hipLaunchKernelGGL(predict_kernel<1>, g, b, 0, st, n3, dt, dt_dev, pos, vel, deriv, pred); break;
+        case 2: hipLaunchKernelGGL(predict_kernel<2>, g, b, 0, st, n3, dt, dt_dev, pos, vel, deriv, pred); break;
+        case 3: hipLaunchKernelGGL(predict_kernel<3>, g, b, 0, st, n3, dt, dt_dev, pos, vel, deriv, pred); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, double *pos, double *vel,
-                          double *deriv, const double *eval, double *pred, hipStream_t st)
+hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
+                          double *vel, double *deriv, const double *eval, double *pred, hipStream_t st)
 {
     const int64_t n3 = 3 * n;
     if (n3 <= 0) return hipSuccess;
     switch (p) {
-        case 1: return correct_p<1>(corrector, last, n3, dt, pos, vel, deriv, eval, pred, st);
-        case 2: return correct_p<2>(corrector, last, n3, dt, pos, vel, deriv, eval, pred, st);
-        case 3: return correct_p<3>(corrector, last, n3, dt, pos, vel, deriv, eval, pred, st);
+        case 1: return correct_p<1>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
+        case 2: return correct_p<2>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
+        case 3: return correct_p<3>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
         default: return hipErrorInvalidValue;
     }
 }

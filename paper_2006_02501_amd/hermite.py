@@ -52,6 +52,10 @@ _SIGS = {
     "hermite_correct": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
     "hermite_step": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
     "hermite_potential": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P]),
+    "hermite_step_criterion": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_double)]),
+    "hermite_step_symmetric": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32,
+                                              ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "hermite_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                             _P, ctypes.POINTER(_P)]),
     "hermite_batch_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
@@ -190,6 +194,19 @@ class Hermite:
 
     def step(self, st, dt, n_iter):
         _check(self.ctx, self.lib.hermite_step(self.ctx, ctypes.byref(st.c), float(dt), int(n_iter)))
+
+    def step_criterion(self, st, eta):
+        """H = eta min over pairs of ((r^2 + eps^2)^(3/2) / (G (m_i + m_j)))^(1/2) at st.pos (Eq. 25)."""
+        h = ctypes.c_double()
+        _check(self.ctx, self.lib.hermite_step_criterion(self.ctx, ctypes.byref(st.c), float(eta), ctypes.byref(h)))
+        return h.value
+
+    def step_symmetric(self, st, eta, n_iter, direction=1.0):
+        """One P(EC)^n step of implicit, time-symmetric length (H_- + H_+)/2 (Sec. 3.3); returns it."""
+        dt = ctypes.c_double()
+        _check(self.ctx, self.lib.hermite_step_symmetric(self.ctx, ctypes.byref(st.c), float(eta), int(n_iter),
+                                                         float(direction), ctypes.byref(dt)))
+        return dt.value
 
     def potential(self, st):
         phi = torch.empty(st.n, dtype=torch.float64, device=self.device)
