@@ -31,6 +31,7 @@ What each function follows (section / equation of the paper):
                            from the Hermite interpolant through a^(0..p) at both
                            ends, solved numerically (confluent Vandermonde).
 * ``step``                 Sec. 2 end / Sec. 3: P(EC)^n iteration.
+* ``kahan_add``            Sec. 3.2: compensated summation (reading R22).
 * ``step_criterion``,      Sec. 3.3, Eq. 25: the minimum two-body time scale
   ``step_symmetric``       and the implicit time-symmetric step (reading R21).
 * ``energy``, ``kepler_elements``  Sec. 3.1 diagnostics; eccentricity vector of
@@ -48,6 +49,11 @@ Readings where the paper is silent (frozen identically in the HIP path):
       with dt = H_-; iteration k corrects with dt = (H_- + H_+)/2, H_+ taken
       at iteration k's evaluation point (the latest estimate of the end of
       the step).  Converged iterations give the time-symmetric step.
+  R22 compensated summation (Sec. 3.2, for the time integration): x, v and t
+      each carry a Kahan compensation term; the corrector adds its increments
+      dv, dx (and the step adds dt) through it.  Every iterate of a step uses
+      the carried terms; the last iteration stores the new ones.  They are
+      part of the state (zero at the start).
 
 Parity pins for every function are in ``tests/test_oracle_*.py``.
 """
@@ -324,14 +330,20 @@ class State:
         self.p = p
         self.derivs = None if derivs is None else [np.array(d, dtype=np.float64).reshape(3, n) for d in derivs]
         self.t = float(t)
+        # compensation terms of x, v and t (reading R22; zero until used)
+        self.cx = np.zeros((3, n))
+        self.cv = np.zeros((3, n))
+        self.tc = 0.0
 
     @property
     def n(self):
         return self.mass.shape[0]
 
     def copy(self):
-        return State(self.mass, self.x, self.v, self.p,
-                     None if self.derivs is None else [d.copy() for d in self.derivs], self.t)
+        c = State(self.mass, self.x, self.v, self.p,
+                  None if self.derivs is None else [d.copy() for d in self.derivs], self.t)
+        c.cx, c.cv, c.tc = self.cx.copy(), self.cv.copy(), self.tc
+        return c
 
 
 def init_derivs(st, G=1.0, eps2=0.0):
@@ -376,13 +388,23 @@ def predict(p, dt, x, v, derivs):
     return path
 
 
-def correct(p, dt, x0, v0, a0, a1, corrector="modified"):
+def kahan_add(s, c, y):
+    """Compensated summation (Kahan 1965), the Sec. 3.2 option: add y to a
+    running sum s whose lost low-order part is c; returns the new (s, c)."""
+    yc = y - c
+    t = s + yc
+    return t, (t - s) - yc
+
+
+def correct(p, dt, x0, v0, a0, a1, corrector="modified", comp=None):
     """Modified Hermite corrector, Eq. 4-8 (Eq. 22-24 for p = 1, 2, 3).
 
     a0, a1 : lists a^(0..p) at the start (0) and end (1) of the step.
     F^+-_n = 1/2 h^n/n! (f^(n)(t+h) +- f^(n)(t-h)), h = dt/2, + for even n and
     - for odd n (the rows of Eq. 8).  Velocity first (f = a, Eq. 6), then
     position (f = v, f^(n) = a^(n-1), Eq. 7) using the new v1.
+    comp = (cx, cv): the increments are added by compensated summation
+    (reading R22) and the new (cx, cv) is returned as a third value.
     """
     h = 0.5 * dt
     cv = [float(c) for c in quadrature_weights(p)]
@@ -393,12 +415,17 @@ def correct(p, dt, x0, v0, a0, a1, corrector="modified"):
         return 0.5 * (h ** n / factorial(n)) * (f1 + s * f0)
 
     dv = sum(cv[n] * fpm(n, a1[n], a0[n]) for n in range(p + 1)) * dt
-    v1 = v0 + dv
+    if comp is None:
+        v1 = v0 + dv
+    else:
+        v1, cv1 = kahan_add(v0, comp[1], dv)
     f1 = [v1] + list(a1[: p + 1])
     f0 = [v0] + list(a0[: p + 1])
     dx = sum(cx[n] * fpm(n, f1[n], f0[n]) for n in range(p + 2)) * dt
-    x1 = x0 + dx
-    return x1, v1
+    if comp is None:
+        return x0 + dx, v1
+    x1, cx1 = kahan_add(x0, comp[0], dx)
+    return x1, v1, (cx1, cv1)
 
 
 def interpolate_higher(p, dt, a0, a1):
@@ -433,13 +460,16 @@ def interpolate_higher(p, dt, a0, a1):
     return out
 
 
-def step(st, dt, n_iter, corrector="modified", G=1.0, eps2=0.0, return_iterates=False):
+def step(st, dt, n_iter, corrector="modified", G=1.0, eps2=0.0, return_iterates=False, compensated=False):
     """One P(EC)^n step (Sec. 2 end, Sec. 3) of the order-2(p+1) scheme.
 
     P : Taylor prediction from the t0 state.
     n times:  E : a1^(0..p) at the current iterate (reading R3 for its a, adot)
               C : v1, x1 from the t0 state and a0, a1 (Eq. 22-24).
     Then a^(p+1..2p-1)(t1) from the interpolant (R2) and the state moves to t1.
+    compensated: x, v and t take their increments by compensated summation
+    (reading R22); every iterate uses the carried compensation, the last one
+    also updates it.
     """
     if n_iter < 1:
         raise ValueError("n_iter must be >= 1")
@@ -447,20 +477,30 @@ def step(st, dt, n_iter, corrector="modified", G=1.0, eps2=0.0, return_iterates=
     a0 = st.derivs[: p + 1]
     path = predict(p, dt, st.x, st.v, st.derivs)
     iterates = []
+    comp = (st.cx, st.cv) if compensated else None
     for _ in range(n_iter):
         out = pair_derivs(st.mass, path, K=p, G=G, eps2=eps2)
         a1 = [out[k] for k in range(p + 1)]
-        x1, v1 = correct(p, dt, st.x, st.v, a0, a1, corrector)
+        res = correct(p, dt, st.x, st.v, a0, a1, corrector, comp)
+        x1, v1 = res[0], res[1]
         path = [x1, v1] + a1[: p - 1]
         iterates.append((x1, v1, a1))
-    higher = interpolate_higher(p, dt, a0, a1)
-    st.x, st.v = x1, v1
-    st.derivs = list(a1) + higher
-    st.t += dt
+    _finish(st, p, dt, a0, a1, x1, v1, res[2] if compensated else None)
     return iterates if return_iterates else st
 
 
-def step_symmetric(st, eta, n_iter, corrector="modified", G=1.0, eps2=0.0, direction=1.0):
+def _finish(st, p, dt, a0, a1, x1, v1, newcomp):
+    higher = interpolate_higher(p, dt, a0, a1)
+    st.x, st.v = x1, v1
+    st.derivs = list(a1) + higher
+    if newcomp is None:
+        st.t += dt
+    else:
+        st.cx, st.cv = newcomp
+        st.t, st.tc = kahan_add(st.t, st.tc, dt)
+
+
+def step_symmetric(st, eta, n_iter, corrector="modified", G=1.0, eps2=0.0, direction=1.0, compensated=False):
     """One P(EC)^n step with the implicit time-symmetric step of Sec. 3.3
     (reading R21).  H_- = H(x0) at the start; the prediction uses dt = H_-;
     every evaluation also gives H at its evaluation point (the current
@@ -474,17 +514,16 @@ def step_symmetric(st, eta, n_iter, corrector="modified", G=1.0, eps2=0.0, direc
     Hm = step_criterion(st.mass, st.x, eta, G, eps2)
     dt = direction * Hm
     path = predict(p, dt, st.x, st.v, st.derivs)
+    comp = (st.cx, st.cv) if compensated else None
     for _ in range(n_iter):
         out = pair_derivs(st.mass, path, K=p, G=G, eps2=eps2)
         a1 = [out[k] for k in range(p + 1)]
         Hp = step_criterion(st.mass, path[0], eta, G, eps2)
         dt = direction * 0.5 * (Hm + Hp)
-        x1, v1 = correct(p, dt, st.x, st.v, a0, a1, corrector)
+        res = correct(p, dt, st.x, st.v, a0, a1, corrector, comp)
+        x1, v1 = res[0], res[1]
         path = [x1, v1] + a1[: p - 1]
-    higher = interpolate_higher(p, dt, a0, a1)
-    st.x, st.v = x1, v1
-    st.derivs = list(a1) + higher
-    st.t += dt
+    _finish(st, p, dt, a0, a1, x1, v1, res[2] if compensated else None)
     return dt
 
 
