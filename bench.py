@@ -7,7 +7,8 @@ a^(2), a^(3); correct), interpolate -- with the state already in HBM.
 Metric: pair interactions per second, n_iter * N (N - 1) per step.  The
 top-level line is the FP64 path; the mixed-precision path is reported beside
 it with its error against the FP64 run.  The batched workload (4096 systems
-of 3..64 bodies, 1000 steps) is reported against one launch per system.
+of 3..64 bodies, 1000 steps) is reported against one launch per system, and
+the disc again with the variable time-symmetric step of Sec. 3.3.
 
 Prints ONE JSON line (N = 1 GPU only).
 """
@@ -156,6 +157,41 @@ def time_mode(precision, w, steps, warmup, autotune=True, launch=None):
     return res, final
 
 
+def variable_step(w, steps, warmup, eta, launch):
+    """The same disc with the implicit time-symmetric step of Sec. 3.3 (FP64,
+    P(EC)^3, the FP64 launch shape): H_- at the start, H_+ at every
+    evaluation point; one host round trip per step (the step length)."""
+    import torch
+    from paper_2006_02501_amd import Hermite
+
+    order, n_iter = w["order"], w["n_iter"]
+    n = len(w["mass"])
+    h = Hermite(order, n, G=w["G"], eps2=w["eps2"], device="cuda:0")
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    if launch is not None:
+        h.set_launch(*launch)
+    for _ in range(warmup):
+        h.step_symmetric(st, eta, n_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dts = [h.step_symmetric(st, eta, n_iter) for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the criterion pass alone (H at the state; includes its copy-back)
+    reps = 10
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        h.step_criterion(st, eta)
+    crit_ms = (time.perf_counter() - t1) / reps * 1e3
+    h.close()
+    inter = n * (n - 1)
+    return {"eta": eta, "n_iter": n_iter, "steps": steps, "ms_per_step": elapsed / steps * 1e3,
+            "interactions_per_s": steps * n_iter * inter / elapsed, "criterion_ms_with_copy": crit_ms,
+            "dt_first": dts[0], "dt_last": dts[-1]}
+
+
 def orbit_diffs(a, b, n_bodies=256):
     """Eccentricity-vector and periapsis differences between two final states
     for the first n_bodies stars relative to the central body."""
@@ -285,6 +321,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-variable-step", action="store_true")
+    ap.add_argument("--eta", type=float, default=0.4,
+                    help="variable-step accuracy parameter (0.4 gives dt near 2 pi / 2000 on this disc)")
     ap.add_argument("--no-per-system", action="store_true",
                     help="skip the one-launch-per-system comparison of the batched workload")
     ap.add_argument("--launch", default=None,
@@ -345,6 +384,15 @@ def main():
     }
     if calib:
         out["copy_calibration"] = calib
+    if not args.no_variable_step:
+        log("  variable step ...")
+        lf = r["launch"]
+        shape = (lf["i_per_thread"], lf["j_split"], 0 if lf["j_source"] == "lds" else 1, lf["wg_waves"]) if lf else None
+        vs = variable_step(w, args.steps, args.warmup, args.eta, shape)
+        vs["over_fixed_step_ms"] = vs["ms_per_step"] / r["ms_per_step"]
+        out["variable_step"] = vs
+        log("  variable step: %.3f ms/step (x%.3f of the fixed step), criterion %.3f ms"
+            % (vs["ms_per_step"], vs["over_fixed_step_ms"], vs["criterion_ms_with_copy"]))
     if not args.no_batched:
         log("  batched ...")
         out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)

@@ -78,6 +78,12 @@ typedef struct {
                               output for inf / NaN (synchronises; E_NONFINITE)     */
     double G;              /* gravitational constant                                */
     double eps2;           /* softening eps^2 >= 0 (Sec. 3: eps = 1e-8 or 1e-6)     */
+    int32_t compensated;   /* nonzero: x, v and t take each step's increments by
+                              compensated (Kahan) summation, the option Sec. 3.2
+                              uses for its 8th-order runs; the state then carries
+                              the compensation terms (comp, t_comp).  Not
+                              available in the batched form (E_ARG there).       */
+    int32_t reserved;      /* set to 0                                              */
 } hermite_params;
 
 /*
@@ -93,7 +99,8 @@ typedef struct {
  *   eval   [p+1][3][n]   a^(0..p) from the latest evaluation
  * t is a host scalar advanced by the last correction of each step.
  * initialized is set to 1 by hermite_init (a caller restoring a saved state
- * sets it itself: (t, mass, pos, vel, deriv) is the complete state).
+ * sets it itself: (t, mass, pos, vel, deriv) is the complete state, plus
+ * (comp, t_comp) with compensated summation).
  */
 typedef struct {
     int64_t n;
@@ -106,6 +113,9 @@ typedef struct {
     double t;
     int32_t initialized;
     int32_t reserved;
+    double *comp;          /* [2][3][n] compensation terms of x and v (used only with
+                              params.compensated; hermite_init zeroes them)       */
+    double t_comp;         /* compensation term of t (same)                         */
 } hermite_state;
 
 /* Create a context for states of up to n_max particles (n_max >= 0).
@@ -126,7 +136,9 @@ hermite_status hermite_set_stream(hermite_ctx *ctx, void *hip_stream);
  * from pos and vel by passes of the generic-order pair derivative
  * (a, adot from x, v; then a^(2), a^(3); then, at 8th order, a^(4), a^(5)),
  * always in FP64.  Writes s->deriv (uses s->eval and s->pred as scratch),
- * sets s->initialized.  E_ARG on NULL pointers or n > n_max. */
+ * zeroes s->comp and s->t_comp with compensated summation, sets
+ * s->initialized.  E_ARG on NULL pointers (comp too, when compensated) or
+ * n > n_max. */
 hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s);
 
 /* Taylor predictor (Sec. 3, second paragraph) with every stored derivative:
@@ -191,7 +203,8 @@ hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, doubl
  * Batched form: n_sys independent systems concatenated in one state
  * (particles offsets[s] .. offsets[s+1]-1 belong to system s; offsets is a
  * HOST array of n_sys+1 nondecreasing values starting at 0, each system of
- * 1..64 particles).  Pair sums run only inside a system.  All steps of all
+ * 1..64 particles).  Pair sums run only inside a system.  params.compensated
+ * must be 0 (E_ARG).  All steps of all
  * systems run in one persistent kernel launch, replayed from a captured HIP
  * graph; systems are packed into 64-lane wavefronts and handed out longest
  * first from a device work counter.

@@ -50,8 +50,10 @@ int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, const double *pos, const double *vel,
                           const double *deriv, double *pred, hipStream_t st);
 
+// comp: [2][3][n] Kahan compensation of x and v, or null for plain addition.
 hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
-                          double *vel, double *deriv, const double *eval, double *pred, hipStream_t st);
+                          double *vel, double *deriv, const double *eval, double *pred, double *comp,
+                          hipStream_t st);
 
 // Time-step criterion (Sec. 3.3): number of workgroup maxima the rate pass
 // writes for n particles (and its j-split).

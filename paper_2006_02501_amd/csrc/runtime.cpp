@@ -99,6 +99,7 @@ hermite_status check_params(const hermite_params *prm, std::string &msg)
     if (prm->corrector < 0 || prm->corrector > 2) { msg = "hermite: unknown corrector"; return HERMITE_E_ARG; }
     if (!std::isfinite(prm->G)) { msg = "hermite: G must be finite"; return HERMITE_E_ARG; }
     if (!std::isfinite(prm->eps2) || prm->eps2 < 0.0) { msg = "hermite: eps2 must be finite and >= 0"; return HERMITE_E_ARG; }
+    if (prm->compensated != 0 && prm->compensated != 1) { msg = "hermite: compensated must be 0 or 1"; return HERMITE_E_ARG; }
     return HERMITE_OK;
 }
 
@@ -112,12 +113,30 @@ hermite_status check_state(hermite_ctx *ctx, const hermite_state *s, bool need_i
             return fail(ctx, HERMITE_E_ARG, "hermite: state has a NULL mass/pos/vel/deriv pointer");
         if (need_pred_eval && (!s->pred || !s->eval))
             return fail(ctx, HERMITE_E_ARG, "hermite: state has a NULL pred/eval pointer");
+        if (ctx->prm.compensated && !s->comp)
+            return fail(ctx, HERMITE_E_ARG, "hermite: compensated summation needs the state's comp array");
     }
     if (need_init && !s->initialized) return fail(ctx, HERMITE_E_STATE, "hermite: state not initialised (hermite_init)");
     return HERMITE_OK;
 }
 
 bool good_dt(double dt) { return std::isfinite(dt) && dt != 0.0; }
+
+// t advances by dt: plainly, or by compensated summation with the state's
+// t_comp (the same rule the corrector applies to x and v).
+void advance_time(const hermite_ctx *ctx, hermite_state *s, double dt)
+{
+    if (!ctx->prm.compensated) {
+        s->t += dt;
+        return;
+    }
+    const double y = dt - s->t_comp;
+    const double t1 = s->t + y;
+    s->t_comp = (t1 - s->t) - y;
+    s->t = t1;
+}
+
+double *comp_of(const hermite_ctx *ctx, hermite_state *s) { return ctx->prm.compensated ? s->comp : nullptr; }
 
 int64_t partial_capacity(int64_t n_max, int p)
 {
@@ -277,6 +296,11 @@ hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s)
     if (st != HERMITE_OK) return st;
     const int p = ctx->p;
     const int64_t n3 = 3 * s->n;
+    if (ctx->prm.compensated) {
+        s->t_comp = 0.0;
+        if (s->n > 0)
+            HIP_TRY(ctx, hipMemsetAsync(s->comp, 0, (size_t)2 * n3 * sizeof(double), ctx->stream), "comp clear");
+    }
     if (s->n > 0) {
         // pass 1: a, adot from (x, v)
         const double *path[hermite::kMaxPath] = {s->pos, s->vel};
@@ -329,9 +353,9 @@ hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, in
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
     HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, nullptr, s->pos, s->vel,
-                                         s->deriv, s->eval, s->pred, ctx->stream),
+                                         s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
             "correct launch");
-    if (last_iter) s->t += dt;
+    if (last_iter) advance_time(ctx, s, dt);
     return HERMITE_OK;
 }
 
@@ -404,7 +428,7 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
                                               ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
                 "step criterion launch");
         HIP_TRY(ctx, hermite::launch_correct(p, ctx->prm.corrector, it == n_iter - 1 ? 1 : 0, s->n, 0.0, dtp, s->pos,
-                                             s->vel, s->deriv, s->eval, s->pred, ctx->stream),
+                                             s->vel, s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
                 "correct launch");
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
@@ -415,7 +439,7 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
                     "hermite: step criterion not finite and positive (no pair with G (m_i + m_j) > 0, "
                     "coincident bodies without softening, or non-finite positions); state unchanged");
     const double dt = ctx->host_vs[1];
-    s->t += dt;
+    advance_time(ctx, s, dt);
     if (dt_taken) *dt_taken = dt;
     if (!ctx->prm.check_finite) return HERMITE_OK;
     const double *arrs[3] = {s->pos, s->vel, s->deriv};
@@ -525,6 +549,7 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
     *out = nullptr;
     hermite_status st = check_params(prm, msg);
     if (st != HERMITE_OK) return st;
+    if (prm->compensated) return HERMITE_E_ARG;   // the batched kernel adds plainly
     if (n_sys < 0 || (n_sys > 0 && !offsets)) return HERMITE_E_ARG;
     if (n_sys > 0 && offsets[0] != 0) return HERMITE_E_ARG;
     int32_t max_size = 0;

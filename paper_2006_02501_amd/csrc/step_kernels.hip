@@ -57,13 +57,17 @@ __global__ __launch_bounds__(kStepBlock) void predict_kernel(int64_t n3, double 
 // a^(P+1..2P-1) at the end of the step.  dt as in the predictor; a device
 // dt of exactly 0 marks a step whose length could not be formed, and then
 // nothing is written.
+// With comp ([2][3][n], x then v) the increments dt*dv and dt*dx are added
+// by Kahan's compensated summation (the option of Sec. 3.2): y = inc - c,
+// s' = s + y, c' = (s' - s) - y.  Every iterate uses the carried c; the last
+// iteration stores c'.
 template <int P, int CORR>
 __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double dt_host,
                                                              const double *__restrict__ dt_dev, int last,
                                                              double *__restrict__ pos,
                                                              double *__restrict__ vel, double *__restrict__ deriv,
                                                              const double *__restrict__ eval,
-                                                             double *__restrict__ pred)
+                                                             double *__restrict__ pred, double *__restrict__ comp)
 {
     const int64_t e = (int64_t)blockIdx.x * kStepBlock + threadIdx.x;
     const double dt = dt_dev ? dt_dev[0] : dt_host;
@@ -82,7 +86,14 @@ __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double 
         const double s = (k & 1) ? (a1[k] - a0[k]) : (a1[k] + a0[k]);
         dv = __builtin_fma(dv, dt, CV[P][k] * s);
     }
-    const double v1 = __builtin_fma(dv, dt, v0);
+    double v1, cv1 = 0.0;
+    if (comp) {
+        const double y = dv * dt - comp[n3 + e];
+        v1 = v0 + y;
+        cv1 = (v1 - v0) - y;
+    } else {
+        v1 = __builtin_fma(dv, dt, v0);
+    }
     // q^(0) = v, q^(k) = a^(k-1)
     double dx = 0.0;
 #pragma unroll
@@ -91,7 +102,14 @@ __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double 
         dx = __builtin_fma(dx, dt, CX[CORR][P][k] * s);
     }
     dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1 + v0));
-    const double x1 = __builtin_fma(dx, dt, x0);
+    double x1, cx1 = 0.0;
+    if (comp) {
+        const double y = dx * dt - comp[e];
+        x1 = x0 + y;
+        cx1 = (x1 - x0) - y;
+    } else {
+        x1 = __builtin_fma(dx, dt, x0);
+    }
     if (!last) {
         // next iterate: (x1, v1) and the evaluated a, adot as the relative path
         pred[e] = x1;
@@ -102,6 +120,10 @@ __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double 
     }
     pos[e] = x1;
     vel[e] = v1;
+    if (comp) {
+        comp[e] = cx1;
+        comp[n3 + e] = cv1;
+    }
     if constexpr (P == 2) {
         const double t1 = dt, t2 = dt * dt;
         const double num = I6_A0[0] * a0[0] + I6_A1[0] * a1[0] + (I6_A0[1] * a0[1] + I6_A1[1] * a1[1]) * t1 +
@@ -171,13 +193,13 @@ inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kStepBloc
 
 template <int P>
 hipError_t correct_p(int corrector, int last, int64_t n3, double dt, const double *dt_dev, double *pos, double *vel,
-                     double *deriv, const double *eval, double *pred, hipStream_t st)
+                     double *deriv, const double *eval, double *pred, double *comp, hipStream_t st)
 {
     const dim3 g(blocks_for(n3)), b(kStepBlock);
     switch (corrector) {
-        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
-        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
-        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred); break;
+        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
+        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
+        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -201,14 +223,15 @@ hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, con
 }
 
 hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
-                          double *vel, double *deriv, const double *eval, double *pred, hipStream_t st)
+                          double *vel, double *deriv, const double *eval, double *pred, double *comp,
+                          hipStream_t st)
 {
     const int64_t n3 = 3 * n;
     if (n3 <= 0) return hipSuccess;
     switch (p) {
-        case 1: return correct_p<1>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
-        case 2: return correct_p<2>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
-        case 3: return correct_p<3>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, st);
+        case 1: return correct_p<1>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
+        case 2: return correct_p<2>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
+        case 3: return correct_p<3>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
         default: return hipErrorInvalidValue;
     }
 }

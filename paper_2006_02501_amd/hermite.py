@@ -28,14 +28,15 @@ class HermiteError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("corrector", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32), ("G", ctypes.c_double), ("eps2", ctypes.c_double)]
+                ("check_finite", ctypes.c_int32), ("G", ctypes.c_double), ("eps2", ctypes.c_double),
+                ("compensated", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class StateC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mass", ctypes.c_void_p), ("pos", ctypes.c_void_p),
                 ("vel", ctypes.c_void_p), ("deriv", ctypes.c_void_p), ("pred", ctypes.c_void_p),
                 ("eval", ctypes.c_void_p), ("t", ctypes.c_double), ("initialized", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("comp", ctypes.c_void_p), ("t_comp", ctypes.c_double)]
 
 
 _lib = None
@@ -109,8 +110,10 @@ class DeviceState:
         if with_pred:
             self.pred = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
             self.eval = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
+            # compensation terms of x and v (used with compensated summation)
+            self.comp = torch.zeros((2, 3, n), dtype=torch.float64, device=dev)
         else:
-            self.pred = self.eval = None
+            self.pred = self.eval = self.comp = None
         self.c = StateC()
         self.c.n = n
         self.c.mass = self.mass.data_ptr()
@@ -119,7 +122,9 @@ class DeviceState:
         self.c.deriv = self.deriv.data_ptr()
         self.c.pred = self.pred.data_ptr() if with_pred else None
         self.c.eval = self.eval.data_ptr() if with_pred else None
+        self.c.comp = self.comp.data_ptr() if with_pred else None
         self.c.t = float(t)
+        self.c.t_comp = 0.0
         self.c.initialized = 0
 
     @property
@@ -145,6 +150,8 @@ class DeviceState:
         if self.pred is not None:
             d["pred"] = [q for q in self.pred.cpu().numpy()]
             d["eval"] = [q for q in self.eval.cpu().numpy()]
+            comp = self.comp.cpu().numpy()
+            d["cx"], d["cv"], d["t_comp"] = comp[0], comp[1], self.c.t_comp
         return d
 
 
@@ -152,13 +159,13 @@ class Hermite:
     """One integrator context (hermite_create) bound to a torch device and stream."""
 
     def __init__(self, order, n_max, precision="fp64", corrector="modified", G=1.0, eps2=0.0,
-                 check_finite=False, device="cuda:0"):
+                 check_finite=False, device="cuda:0", compensated=False):
         self.lib = load_library()
         self.order = order
         self.p = order // 2 - 1
         self.device = torch.device(device)
         self.prm = Params(order, PRECISIONS[precision], CORRECTORS[corrector], 1 if check_finite else 0,
-                          float(G), float(eps2))
+                          float(G), float(eps2), 1 if compensated else 0, 0)
         self.ctx = ctypes.c_void_p()
         _check(None, self.lib.hermite_create(ctypes.byref(self.prm), int(n_max), _stream_handle(self.device),
                                              ctypes.byref(self.ctx)))
@@ -176,6 +183,16 @@ class Hermite:
 
     def state(self, mass, x, v, t=0.0):
         return DeviceState(self.p, mass, x, v, self.device, t)
+
+    def restore(self, snap):
+        """A state from ``DeviceState.host()`` output (checkpoint/resume), marked initialised."""
+        st = DeviceState(self.p, snap["mass"], snap["x"], snap["v"], self.device, snap["t"])
+        st.deriv.copy_(torch.as_tensor(np.stack(snap["derivs"])))
+        if "cx" in snap:
+            st.comp.copy_(torch.as_tensor(np.stack([snap["cx"], snap["cv"]])))
+            st.c.t_comp = float(snap["t_comp"])
+        st.mark_initialized()
+        return st
 
     def use_current_stream(self):
         _check(self.ctx, self.lib.hermite_set_stream(self.ctx, _stream_handle(self.device)))

@@ -4,6 +4,7 @@ include/hermite.h declares, and validates arguments before any HIP call
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -32,10 +33,11 @@ def test_every_declared_symbol_exported():
 
 def _create(**kw):
     lib = load_library()
-    prm = dict(order=8, precision=0, corrector=0, check_finite=0, G=1.0, eps2=0.0)
+    prm = dict(order=8, precision=0, corrector=0, check_finite=0, G=1.0, eps2=0.0, compensated=0)
     n_max = kw.pop("n_max", 16)
     prm.update(kw)
-    p = Params(prm["order"], prm["precision"], prm["corrector"], prm["check_finite"], prm["G"], prm["eps2"])
+    p = Params(prm["order"], prm["precision"], prm["corrector"], prm["check_finite"], prm["G"], prm["eps2"],
+               prm["compensated"], 0)
     ctx = ctypes.c_void_p()
     st = lib.hermite_create(ctypes.byref(p), n_max, None, ctypes.byref(ctx))
     return st, ctx
@@ -45,7 +47,7 @@ def _create(**kw):
     (dict(order=5), -2), (dict(order=10), -2), (dict(order=0), -2),
     (dict(precision=2), -1), (dict(corrector=3), -1), (dict(corrector=-1), -1),
     (dict(eps2=-1e-9), -1), (dict(eps2=float("nan")), -1), (dict(G=float("inf")), -1),
-    (dict(n_max=-1), -1),
+    (dict(n_max=-1), -1), (dict(compensated=2), -1), (dict(compensated=-1), -1),
 ])
 def test_create_rejects_bad_params(kw, code):
     st, ctx = _create(**kw)
@@ -86,6 +88,38 @@ def test_batch_create_rejects_bad_layout(offsets):
                                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None, ctypes.byref(ctx))
     assert st == -1
     assert not ctx.value
+
+
+def test_batch_create_rejects_compensated_summation():
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    p = Params(8, 0, 0, 0, 1.0, 0.0, 1, 0)
+    off = np.array([0, 3], dtype=np.int64)
+    assert lib.hermite_batch_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    None, ctypes.byref(ctx)) == -1
+    assert not ctx.value
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the binding's ctypes structures against the C compiler's layout of the header
+    fields = {Params: ("hermite_params", [f[0] for f in Params._fields_]),
+              StateC: ("hermite_state", [f[0] for f in StateC._fields_])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hermite.h"', "int main(void) {"]
+    for cls, (cname, names) in fields.items():
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for f in names:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    for cls, (cname, names) in fields.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in names:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
 
 
 def test_batch_create_rejects_bad_order_and_null_offsets():

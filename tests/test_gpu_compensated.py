@@ -1,0 +1,162 @@
+"""GPU path with compensated summation in the time integration (Sec. 3.2,
+reading R22): parity with the oracle's compensated steps (fixed and
+variable), the free-particle and Kepler round-off properties on the GPU, and
+checkpoint/resume of the compensation terms."""
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hermite_oracle as ho
+from paper_2006_02501_amd import Hermite, HermiteError
+from parity_util import disc_path, rel_max
+from workloads import disc100, kepler_two_body, ring64
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _run_pair(order, w, dt, n_iter, steps, eps2=0.0):
+    p = order // 2 - 1
+    o = ho.State(w["mass"], w["x"], w["v"], p)
+    ho.init_derivs(o, eps2=eps2)
+    n = len(w["mass"])
+    h = Hermite(order, n, eps2=eps2, compensated=True, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    for _ in range(steps):
+        ho.step(o, dt, n_iter, eps2=eps2, compensated=True)
+        h.step(st, dt, n_iter)
+    d = st.host()
+    h.close()
+    return o, d
+
+
+@pytest.mark.parametrize("case", ["kepler4", "kepler8", "ring64", "disc700"])
+def test_compensated_step_parity(case):
+    _say("compensated step parity %s" % case)
+    if case.startswith("kepler"):
+        w = kepler_two_body(e=0.5)
+        order, dt, n_iter = int(case[-1]), w["period"] / 200, 3
+    elif case == "ring64":
+        w = ring64()
+        order, dt, n_iter = 4, w["dt"], w["n_iter"]
+    else:
+        w, _ = disc_path(700, 1)
+        order, dt, n_iter = 8, 2 * np.pi / 2000, 3
+    o, g = _run_pair(order, w, dt, n_iter, 1)
+    assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+    o, g = _run_pair(order, w, dt, n_iter, 50)
+    assert rel_max(g["x"], o.x) <= 1e-11 and rel_max(g["v"], o.v) <= 1e-11
+    # t follows the same compensated rule on the host: bitwise the oracle's
+    assert g["t"] == o.t and g["t_comp"] == o.tc
+    # the compensation terms are rounding-sized
+    assert np.abs(g["cx"]).max() <= 4 * np.spacing(np.abs(g["x"]).max())
+    assert np.abs(g["cv"]).max() <= 4 * np.spacing(np.abs(g["v"]).max())
+
+
+def test_compensated_symmetric_step_parity():
+    _say("compensated symmetric step disc100")
+    w = disc100()
+    o = ho.State(w["mass"], w["x"], w["v"], 3)
+    ho.init_derivs(o, eps2=w["eps2"])
+    h = Hermite(8, len(w["mass"]), eps2=w["eps2"], compensated=True, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    for _ in range(20):
+        do = ho.step_symmetric(o, 0.08, 4, eps2=w["eps2"], compensated=True)
+        dg = h.step_symmetric(st, 0.08, 4)
+        assert abs(dg / do - 1.0) <= 1e-12
+    g = st.host()
+    h.close()
+    assert rel_max(g["x"], o.x) <= 1e-11 and rel_max(g["v"], o.v) <= 1e-11
+    assert g["t"] == pytest.approx(o.t, rel=1e-13)
+
+
+def _free_particle(compensated, steps=10000, dt=0.1):
+    h = Hermite(4, 1, compensated=compensated, device=DEV)
+    st = h.state([1.0], [[0.7], [0.0], [0.0]], [[1.0 / 3.0], [0.0], [0.0]])
+    h.init(st)
+    for _ in range(steps):
+        h.step(st, dt, 1)
+    d = st.host()
+    h.close()
+    inc = Fraction(float(np.float64(1.0 / 3.0) * dt))
+    return d, abs(Fraction(float(d["x"][0, 0])) - (Fraction(0.7) + steps * inc))
+
+
+def test_free_particle_on_gpu():
+    # a = 0: each step adds fl(v dt) once; the exact sum is rational
+    _say("compensated free particle")
+    dc, err_c = _free_particle(True)
+    dp, err_p = _free_particle(False)
+    ulp = Fraction(float(np.spacing(dc["x"][0, 0])))
+    assert err_c <= ulp
+    assert err_p > 50 * ulp
+    assert dc["t"] == 1000.0 and dp["t"] != 1000.0
+
+
+def _kepler_worst_energy(compensated, orbits=4, dt=2.0 ** -5):
+    w = kepler_two_body(e=0.1)
+    h = Hermite(8, 2, eps2=1e-16, compensated=compensated, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    E0 = ho.energy(w["mass"], w["x"], w["v"], eps2=1e-16)
+    worst = 0.0
+    for _ in range(int(orbits * 2 * np.pi / dt)):
+        h.step(st, dt, 3)
+        d = st.host()
+        worst = max(worst, abs(ho.energy(d["mass"], d["x"], d["v"], eps2=1e-16) / E0 - 1.0))
+    h.close()
+    return worst
+
+
+def test_compensation_lowers_round_off_energy_error_on_gpu():
+    # Sec. 3.2: 8th order at a step where truncation is below round-off
+    _say("compensated kepler round-off")
+    plain = _kepler_worst_energy(False)
+    comp = _kepler_worst_energy(True)
+    assert plain < 1e-14
+    assert comp < 0.5 * plain
+
+
+def test_compensated_checkpoint_resume_bitwise():
+    _say("compensated checkpoint resume")
+    w, _ = disc_path(300, 1)
+    dt = 2 * np.pi / 2000
+    h = Hermite(8, 300, compensated=True, device=DEV)
+    a = h.state(w["mass"], w["x"], w["v"])
+    h.init(a)
+    for _ in range(6):
+        h.step(a, dt, 3)
+    b = h.state(w["mass"], w["x"], w["v"])
+    h.init(b)
+    for _ in range(3):
+        h.step(b, dt, 3)
+    c = h.restore(b.host())
+    for _ in range(3):
+        h.step(c, dt, 3)
+    da, dc = a.host(), c.host()
+    for k in ("x", "v", "cx", "cv"):
+        assert np.array_equal(da[k], dc[k]), k
+    assert da["t"] == dc["t"] and da["t_comp"] == dc["t_comp"]
+    assert all(np.array_equal(p, q) for p, q in zip(da["derivs"], dc["derivs"]))
+    h.close()
+
+
+def test_compensated_needs_comp_array():
+    _say("compensated without comp")
+    w = kepler_two_body(e=0.5)
+    h = Hermite(8, 2, compensated=True, device=DEV)
+    st = h.state(w["mass"], w["x"], w["v"])
+    st.c.comp = None
+    with pytest.raises(HermiteError) as ei:
+        h.init(st)
+    assert ei.value.status == -1
+    h.close()
