@@ -6,7 +6,8 @@ A timed step is one whole P(EC)^3 step -- predict, 3 x (evaluate a, adot,
 a^(2), a^(3); correct), interpolate -- with the state already in HBM.
 Metric: pair interactions per second, n_iter * N (N - 1) per step.  The
 top-level line is the FP64 path; the mixed-precision path is reported beside
-it with its error against the FP64 run.  The batched workload (4096 systems
+it, and so is the split path (FP64 a and adot, FP32 higher derivatives),
+each with its difference from the FP64 run.  The batched workload (4096 systems
 of 3..64 bodies, 1000 steps) is reported against one launch per system, and
 the disc again with the variable time-symmetric step of Sec. 3.3.
 
@@ -61,7 +62,7 @@ MEASURED_TRAFFIC = {
 }
 # MI355X published vector peaks: 256 CUs x 4 SIMD16 x 2 flops (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s FP64; FP32 twice that (157.3) with packed-FP32 issue.
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "split": 78.6}
 
 
 def log(*a):
@@ -348,13 +349,14 @@ def main():
             k, v = part.split("=")
             fixed[k.strip()] = tuple(int(x) for x in v.split(","))
     res, fin = {}, {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "split"):
         res[prec], fin[prec] = time_mode(prec, w, args.steps, args.warmup, autotune=not args.no_autotune,
                                          launch=fixed.get(prec))
         log("  %s: %.3e interactions/s, %.3f ms/step, eval %.3f ms, launch %s"
             % (prec, res[prec]["value"], res[prec]["ms_per_step"], res[prec]["eval_ms_avg"], res[prec]["launch"]))
-    r, mx = res["fp64"], res["mixed"]
+    r, mx, sp = res["fp64"], res["mixed"], res["split"]
     de, dw = orbit_diffs(fin["fp64"], fin["mixed"])
+    sde, sdw = orbit_diffs(fin["fp64"], fin["split"])
     out = {
         "metric": "pair interactions/sec for 8th-order derivs at N=16k: mixed vs FP64, 1 GPU",
         "value": r["value"],
@@ -381,6 +383,12 @@ def main():
                                "max_ecc_vector_diff": de, "max_periapsis_diff_rad": dw,
                                "bodies_compared": 256, "after_steps": args.steps + args.warmup}),
         "mixed_over_fp64": mx["value"] / r["value"],
+        "split": dict({k: v for k, v in sp.items() if k != "roofline"},
+                      dtype="f64 a and adot, f32 a^(2) and a^(3) chain",
+                      vs_fp64={"energy_rel_change_diff": sp["energy_rel_change"] - r["energy_rel_change"],
+                               "max_ecc_vector_diff": sde, "max_periapsis_diff_rad": sdw,
+                               "bodies_compared": 256, "after_steps": args.steps + args.warmup}),
+        "split_over_fp64": sp["value"] / r["value"],
     }
     if calib:
         out["copy_calibration"] = calib

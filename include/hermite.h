@@ -53,11 +53,15 @@ typedef enum {
 
 typedef enum {
     HERMITE_FP64 = 0,   /* every operation in FP64                                   */
-    HERMITE_MIXED = 1   /* FP64 state and pairwise differences; the r^-3 pair term
-                           and its derivative chain in FP32, summed in FP32 within
-                           a j-tile and in FP64 across tiles (the paper suggests
-                           lower precision for the higher-order terms on
-                           accelerators, Sec. 4)                                   */
+    HERMITE_MIXED = 1,  /* FP64 state and pairwise differences; the r^-3 pair term
+                           and its derivative chain in FP32, summed in FP32 over
+                           32 j at a time and in FP64 across those sums          */
+    HERMITE_SPLIT = 2   /* the paper's own suggestion (Sec. 4: lower precision for
+                           the higher-order terms on accelerators): a and adot
+                           exactly as HERMITE_FP64 computes them (bitwise, for a
+                           given launch shape), a^(2) and a^(3) in FP32 as in
+                           HERMITE_MIXED.  At 4th order it is HERMITE_FP64.
+                           Not available in the batched form (E_ARG there).      */
 } hermite_precision;
 
 typedef enum {

@@ -17,8 +17,9 @@
 // Chains: FP64 (everything double); Mixed (differences of the FP64 path in
 // double, then cast; the r^-3 term and its derivative chain in float,
 // summed in float over 32 j at a time and in double across those partial
-// sums); Generic (the FP64 recurrence up to the 5th derivative, for the
-// initialisation).
+// sums); Split (a and adot as in FP64, a^(2) and a^(3) as in Mixed, from the
+// same FP64 differences); Generic (the FP64 recurrence up to the 5th
+// derivative, for the initialisation).
 #include "kernels.h"
 #include "pair_chain.h"
 
@@ -30,8 +31,29 @@ struct Path {
     const double *p[K + 1];
 };
 
-constexpr int kFold = 32;   // mixed chain: j-particles per FP32 partial sum
+constexpr int kFold = 32;   // mixed / split chains: j-particles per FP32 partial sum
 constexpr int kWave = 64;   // lanes per wavefront
+
+// Chains with FP32 partial sums (folded into FP64 every kFold j), and the
+// first derivative order they keep in FP32.
+template <Chain CH>
+constexpr bool folds() { return CH == Chain::Mixed || CH == Chain::Split; }
+template <Chain CH>
+constexpr int first_f32() { return CH == Chain::Split ? 2 : 0; }
+
+template <int K, Chain CH, int IPT>
+__device__ __forceinline__ void fold_partials(double (&acc)[IPT][K + 1][3], float (&accf)[IPT][K + 1][3])
+{
+#pragma unroll
+    for (int q = 0; q < IPT; ++q)
+#pragma unroll
+        for (int k = first_f32<CH>(); k <= K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[q][k][c] += (double)accf[q][k][c];
+                accf[q][k][c] = 0.0f;
+            }
+}
 
 // i-particles per workgroup of W waves: 64*IPT when the waves share them
 // (and split the j-range), else 64*W*IPT.
@@ -90,6 +112,26 @@ __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const
                 const float rinv2 = rinv * rinv;
                 const float mr3 = m * rinv * rinv2;
                 chain_accumulate<K, float>(r, v, a, j, mr3, rinv2, accf[q]);
+            } else if constexpr (CH == Chain::Split) {
+                double r[3], v[3];
+                float a[3], j[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = row[1 + c] - xi[q][0][c];
+                    v[c] = row[4 + c] - xi[q][1][c];
+                    a[c] = (float)(row[7 + c] - xi[q][2][c]);
+                    if constexpr (K >= 3) j[c] = (float)(row[10 + c] - xi[q][3][c]); else j[c] = 0.0f;
+                }
+                double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                double m = row[0];
+                if (DIAG) {
+                    w = self ? 1.0 : w;
+                    m = self ? 0.0 : m;
+                }
+                const double rinv = rsqrt64(w);
+                const double rinv2 = rinv * rinv;
+                const double mr3 = m * rinv * rinv2;
+                chain_split<K>(r, v, a, j, mr3, rinv2, acc[q], accf[q]);
             } else {
                 double r[K + 1][3];
 #pragma unroll
@@ -194,7 +236,7 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
         // rows of this tile that this lane's wave handles
         const int r0 = SHARE ? min(cnt, wave * kWave) : 0;
         const int r1 = SHARE ? min(cnt, r0 + kWave) : cnt;
-        if constexpr (CH != Chain::Mixed) {
+        if constexpr (!folds<CH>()) {
             if (r1 > r0) {
                 if (diag)
                     tile_pass<K, CH, IPT, true, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc, accf);
@@ -210,15 +252,7 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
                     tile_pass<K, CH, IPT, true, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
                 else
                     tile_pass<K, CH, IPT, false, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
-#pragma unroll
-                for (int q = 0; q < IPT; ++q)
-#pragma unroll
-                    for (int k = 0; k <= K; ++k)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            acc[q][k][c] += (double)accf[q][k][c];
-                            accf[q][k][c] = 0.0f;
-                        }
+                fold_partials<K, CH, IPT>(acc, accf);
             }
         }
     }
@@ -316,6 +350,25 @@ __device__ __forceinline__ void stream_range(const double *__restrict__ jrec, in
                 const double rinv = rsqrt64(w);
                 const double rinv2 = rinv * rinv;
                 chain_accumulate<K, double>(r, v, a, jk, m * rinv * rinv2, rinv2, acc[q]);
+            } else if constexpr (CH == Chain::Split) {
+                double r[3], v[3];
+                float a[3], jk[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = jd[1 + c] - xi[q][0][c];
+                    v[c] = jd[4 + c] - xi[q][1][c];
+                    a[c] = (float)(jd[7 + c] - xi[q][2][c]);
+                    if constexpr (K >= 3) jk[c] = (float)(jd[10 + c] - xi[q][3][c]); else jk[c] = 0.0f;
+                }
+                double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                double m = jd[0];
+                if (DIAG) {
+                    w = self ? 1.0 : w;
+                    m = self ? 0.0 : m;
+                }
+                const double rinv = rsqrt64(w);
+                const double rinv2 = rinv * rinv;
+                chain_split<K>(r, v, a, jk, m * rinv * rinv2, rinv2, acc[q], accf[q]);
             } else {
                 float r[3], v[3], a[3], jk[3];
 #pragma unroll
@@ -345,21 +398,13 @@ __device__ __forceinline__ void stream_folded(const double *__restrict__ jrec, i
                                               double eps2, double (&acc)[IPT][K + 1][3],
                                               float (&accf)[IPT][K + 1][3])
 {
-    if constexpr (CH != Chain::Mixed) {
+    if constexpr (!folds<CH>()) {
         stream_range<K, CH, IPT, DIAG>(jrec, jb, je, ii, xi, eps2, acc, accf);
     } else {
         for (int64_t s0 = jb; s0 < je; s0 += kFold) {
             const int64_t s1 = min(je, s0 + (int64_t)kFold);
             stream_range<K, CH, IPT, DIAG>(jrec, s0, s1, ii, xi, eps2, acc, accf);
-#pragma unroll
-            for (int q = 0; q < IPT; ++q)
-#pragma unroll
-                for (int k = 0; k <= K; ++k)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        acc[q][k][c] += (double)accf[q][k][c];
-                        accf[q][k][c] = 0.0f;
-                    }
+            fold_partials<K, CH, IPT>(acc, accf);
         }
     }
 }
@@ -501,6 +546,14 @@ hipError_t dispatch(const ForceArgs &a, const LaunchShape &sh, int nsplit, int64
             case 5: return launch_lds<5, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
             default: return hipErrorInvalidValue;
         }
+    } else if constexpr (CH == Chain::Split) {
+        // 4th order has no FP32 part: the split chain is the FP64 one
+        switch (a.K) {
+            case 1: return dispatch_k<1, Chain::Fp64>(a, sh, nsplit, j_chunk, dst, st);
+            case 2: return dispatch_k<2, CH>(a, sh, nsplit, j_chunk, dst, st);
+            case 3: return dispatch_k<3, CH>(a, sh, nsplit, j_chunk, dst, st);
+            default: return hipErrorInvalidValue;
+        }
     } else {
         switch (a.K) {
             case 1: return dispatch_k<1, CH>(a, sh, nsplit, j_chunk, dst, st);
@@ -558,6 +611,7 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, 
     switch (chain) {
         case Chain::Fp64: e = dispatch<Chain::Fp64>(a, sh, nsplit, j_chunk, dst, st); break;
         case Chain::Mixed: e = dispatch<Chain::Mixed>(a, sh, nsplit, j_chunk, dst, st); break;
+        case Chain::Split: e = dispatch<Chain::Split>(a, sh, nsplit, j_chunk, dst, st); break;
         default: e = dispatch<Chain::Generic>(a, sh, nsplit, j_chunk, dst, st); break;
     }
     if (e != hipSuccess || nsplit == 1) return e;

@@ -10,7 +10,7 @@ constexpr int kBlock = 256;   // threads per workgroup of the tiled evaluation (
 constexpr int kTile = 256;    // j-particles staged in LDS per tile
 constexpr int kMaxPath = 6;   // path derivatives x^(0..5) (generic initialisation)
 
-enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2 };
+enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2, Split = 3 };
 
 // Where the evaluation reads the j-particles from: LDS tiles filled by the
 // workgroup, or packed records streamed through the scalar unit into SGPRs.

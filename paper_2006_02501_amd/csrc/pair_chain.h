@@ -101,6 +101,58 @@ __device__ __forceinline__ void chain_accumulate(const T (&r)[3], const T (&v)[3
     }
 }
 
+// Split precision (Sec. 4: lower precision for the higher derivatives only):
+// a and adot exactly as chain_accumulate<K, double> forms them (the same
+// operations, so the same bits), a^(2) and a^(3) in FP32 from the FP32 casts
+// of the relative path and of alpha, J' and the FP64 factors.
+template <int K>
+__device__ __forceinline__ void chain_split(const double (&r)[3], const double (&v)[3], const float (&af)[3],
+                                            const float (&jf)[3], double mr3, double rinv2, double (&acc)[K + 1][3],
+                                            float (&accf)[K + 1][3])
+{
+    static_assert(K >= 2 && K <= 3, "the split chain has FP32 orders 2..K");
+    const double rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
+    const double alpha = rv * rinv2;
+    const double n1 = -3.0 * alpha;
+    float Jf[3], rf[3], vf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[0][c] = fma_t(mr3, r[c], acc[0][c]);
+        const double J = fma_t(n1, r[c], v[c]);
+        acc[1][c] = fma_t(mr3, J, acc[1][c]);
+        Jf[c] = (float)J;
+        rf[c] = (float)r[c];
+        vf[c] = (float)v[c];
+    }
+    const float alf = (float)alpha, r2f = (float)rinv2, mf = (float)mr3;
+    const float vv = fma_t(vf[2], vf[2], fma_t(vf[1], vf[1], vf[0] * vf[0]));
+    const float ra = fma_t(rf[2], af[2], fma_t(rf[1], af[1], rf[0] * af[0]));
+    const float alpha2 = alf * alf;
+    const float beta = fma_t(vv + ra, r2f, alpha2);
+    const float n1f = -3.0f * alf;
+    const float n2 = 2.0f * n1f;                 // -6 alpha
+    const float n3 = -3.0f * beta;               // -3 beta
+    float S[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        S[c] = fma_t(n3, rf[c], fma_t(n2, Jf[c], af[c]));
+        accf[2][c] = fma_t(mf, S[c], accf[2][c]);
+    }
+    if constexpr (K >= 3) {
+        const float va = fma_t(vf[2], af[2], fma_t(vf[1], af[1], vf[0] * af[0]));
+        const float rj = fma_t(rf[2], jf[2], fma_t(rf[1], jf[1], rf[0] * jf[0]));
+        const float gamma = fma_t(fma_t(3.0f, va, rj), r2f, alf * fma_t(-4.0f, alpha2, -1.0f * n3));
+        const float n4 = 3.0f * n1f;             // -9 alpha
+        const float n5 = 3.0f * n3;              // -9 beta
+        const float n6 = -3.0f * gamma;          // -3 gamma
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float C = fma_t(n6, rf[c], fma_t(n5, Jf[c], fma_t(n4, S[c], jf[c])));
+            accf[3][c] = fma_t(mf, C, accf[3][c]);
+        }
+    }
+}
+
 // Binomial coefficient (compile time).
 __host__ __device__ constexpr double binom(int n, int k)
 {

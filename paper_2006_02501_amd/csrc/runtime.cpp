@@ -92,8 +92,8 @@ hermite_status check_params(const hermite_params *prm, std::string &msg)
         msg = "hermite: order must be 4, 6 or 8";
         return HERMITE_E_ORDER;
     }
-    if (prm->precision != HERMITE_FP64 && prm->precision != HERMITE_MIXED) {
-        msg = "hermite: precision must be HERMITE_FP64 or HERMITE_MIXED";
+    if (prm->precision != HERMITE_FP64 && prm->precision != HERMITE_MIXED && prm->precision != HERMITE_SPLIT) {
+        msg = "hermite: precision must be HERMITE_FP64, HERMITE_MIXED or HERMITE_SPLIT";
         return HERMITE_E_ARG;
     }
     if (prm->corrector < 0 || prm->corrector > 2) { msg = "hermite: unknown corrector"; return HERMITE_E_ARG; }
@@ -342,7 +342,9 @@ hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
     const int64_t n3 = 3 * s->n;
     const double *path[hermite::kMaxPath] = {};
     for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
-    const Chain ch = ctx->prm.precision == HERMITE_MIXED ? Chain::Mixed : Chain::Fp64;
+    const Chain ch = ctx->prm.precision == HERMITE_MIXED   ? Chain::Mixed
+                     : ctx->prm.precision == HERMITE_SPLIT ? Chain::Split
+                                                           : Chain::Fp64;
     return run_force(ctx, s, ch, p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves);
 }
 
@@ -550,6 +552,7 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
     hermite_status st = check_params(prm, msg);
     if (st != HERMITE_OK) return st;
     if (prm->compensated) return HERMITE_E_ARG;   // the batched kernel adds plainly
+    if (prm->precision == HERMITE_SPLIT) return HERMITE_E_ARG;
     if (n_sys < 0 || (n_sys > 0 && !offsets)) return HERMITE_E_ARG;
     if (n_sys > 0 && offsets[0] != 0) return HERMITE_E_ARG;
     int32_t max_size = 0;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhermite.so")
 
 HERMITE_OK = 0
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_ORDER", -3: "E_ALLOC", -4: "E_HIP", -5: "E_NONFINITE", -6: "E_STATE"}
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "split": 2}
 CORRECTORS = {"modified": 0, "beta1": 1, "shifted": 2}
 
 

@@ -45,7 +45,7 @@ def _create(**kw):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(order=5), -2), (dict(order=10), -2), (dict(order=0), -2),
-    (dict(precision=2), -1), (dict(corrector=3), -1), (dict(corrector=-1), -1),
+    (dict(precision=3), -1), (dict(corrector=3), -1), (dict(corrector=-1), -1),
     (dict(eps2=-1e-9), -1), (dict(eps2=float("nan")), -1), (dict(G=float("inf")), -1),
     (dict(n_max=-1), -1), (dict(compensated=2), -1), (dict(compensated=-1), -1),
 ])
@@ -90,10 +90,11 @@ def test_batch_create_rejects_bad_layout(offsets):
     assert not ctx.value
 
 
-def test_batch_create_rejects_compensated_summation():
+@pytest.mark.parametrize("precision,compensated", [(0, 1), (2, 0)])
+def test_batch_create_rejects_compensated_and_split(precision, compensated):
     lib = load_library()
     ctx = ctypes.c_void_p()
-    p = Params(8, 0, 0, 0, 1.0, 0.0, 1, 0)
+    p = Params(8, precision, 0, 0, 1.0, 0.0, compensated, 0)
     off = np.array([0, 3], dtype=np.int64)
     assert lib.hermite_batch_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     None, ctypes.byref(ctx)) == -1
