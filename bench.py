@@ -9,7 +9,8 @@ top-level line is the FP64 path; the mixed-precision path is reported beside
 it, and so is the split path (FP64 a and adot, FP32 higher derivatives),
 each with its difference from the FP64 run.  The batched workload (4096 systems
 of 3..64 bodies, 1000 steps) is reported against one launch per system, and
-the disc again with the variable time-symmetric step of Sec. 3.3.
+the disc again with the variable time-symmetric step of Sec. 3.3, and the
+2000-orbit iteration-count sweep of Sec. 3.1 (batched, n = 1..4 side by side).
 
 Prints ONE JSON line (N = 1 GPU only).
 """
@@ -32,7 +33,7 @@ FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
 # is reported only while their hash and the launch shape (which fixes the
 # split workspace) match what was profiled.
 KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/pair_chain.h",
-                  "paper_2006_02501_amd/csrc/kernels.h"]
+                  "paper_2006_02501_amd/csrc/force_launch.h"]
 # HBM bytes per evaluation launch (force kernel + split reduction), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
@@ -310,6 +311,52 @@ def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
     return out
 
 
+def fig4_sweep(orbits=2000, chunks=20):
+    """The iteration-count sweep of Sec. 3.1 (Fig. 4): Kepler a = 1, e = 0.1,
+    planet 1e-3, dt = 2^-4, eps = 1e-8, n = 1..4 side by side as four systems
+    of one batched launch per order (per-system n), for `orbits` periods.
+    Energy sampled every orbits/chunks periods on the host (two bodies per
+    system); time is the GPU time of the launches (HIP events)."""
+    import torch
+    from paper_2006_02501_amd import BatchHermite
+    from workloads import kepler_two_body
+
+    w = kepler_two_body(e=0.1)
+    dt, eps2 = 2.0 ** -4, 1e-16
+    total = int(round(orbits * w["period"] / dt))
+    per = total // chunks
+    mass = np.tile(w["mass"], 4)
+    x = np.ascontiguousarray(np.tile(w["x"], (1, 4)))
+    v = np.ascontiguousarray(np.tile(w["v"], (1, 4)))
+    off = np.arange(0, 9, 2, dtype=np.int64)
+
+    def energy(m, xx, vv):
+        m, xx, vv = m.reshape(-1, 2), xx.reshape(3, -1, 2), vv.reshape(3, -1, 2)
+        r2 = np.sum((xx[:, :, 1] - xx[:, :, 0]) ** 2, axis=0)
+        return 0.5 * np.sum(m * np.sum(vv * vv, axis=0), axis=1) - m[:, 0] * m[:, 1] / np.sqrt(r2 + eps2)
+
+    out = {"orbits": orbits, "steps": per * chunks, "dt": dt, "n_iter": [1, 2, 3, 4]}
+    for order in (4, 6, 8):
+        bh = BatchHermite(order, off, eps2=eps2, device="cuda:0")
+        st = bh.state(mass, x, v)
+        bh.init(st)
+        E0 = energy(mass, x, v)
+        worst = np.zeros(4)
+        gpu_ms = 0.0
+        for _ in range(chunks):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bh.run(st, np.full(4, dt), per, [1, 2, 3, 4])
+            e1.record()
+            d = st.host()
+            gpu_ms += e0.elapsed_time(e1)
+            worst = np.maximum(worst, np.abs(energy(d["mass"], d["x"], d["v"]) / E0 - 1.0))
+        bh.close()
+        out["order%d" % order] = {"max_abs_dE_over_E": [float(q) for q in worst], "gpu_ms": gpu_ms,
+                                  "us_per_step": gpu_ms * 1e3 / (per * chunks)}
+    return out
+
+
 def calibrate_copy(mib=256, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -334,6 +381,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variable-step", action="store_true")
+    ap.add_argument("--no-fig4", action="store_true", help="skip the 2000-orbit iteration-count sweep")
     ap.add_argument("--eta", type=float, default=0.4,
                     help="variable-step accuracy parameter (0.4 gives dt near 2 pi / 2000 on this disc)")
     ap.add_argument("--no-per-system", action="store_true",
@@ -412,6 +460,10 @@ def main():
         out["variable_step"] = vs
         log("  variable step: %.3f ms/step (x%.3f of the fixed step), criterion %.3f ms"
             % (vs["ms_per_step"], vs["over_fixed_step_ms"], vs["criterion_ms_with_copy"]))
+    if not args.no_fig4:
+        log("  fig4 n-sweep ...")
+        out["fig4_nsweep"] = fig4_sweep()
+        log("  fig4 n-sweep: %s" % json.dumps({k: v for k, v in out["fig4_nsweep"].items() if k.startswith("order")}))
     if not args.no_batched:
         log("  batched ...")
         out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)

@@ -225,6 +225,14 @@ hermite_status hermite_batch_init(hermite_ctx *ctx, hermite_state *s);
 hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys,
                                  int32_t n_steps, int32_t n_iter);
 
+/* The same with an iteration count per system: n_iter_sys is a HOST array
+ * [n_sys] of values in 1..64 (E_ARG otherwise), copied to the device before
+ * the launch.  A bin of systems iterates as often as its largest count; each
+ * system corrects only its own n times and keeps that iterate (the paper's
+ * n-sweep, Sec. 3.1, runs every n side by side this way). */
+hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const double *dt_sys,
+                                       int32_t n_steps, const int32_t *n_iter_sys);
+
 /*
  * Launch-shape tuning for hermite_force_derivs.
  *   i_per_thread   1 or 2 i-particles per lane

@@ -8,7 +8,9 @@
 // predicted / corrected path of the current iterate through LDS.  The only
 // global traffic per bin is the initial load, the final store and one counter
 // increment.  Lanes of different systems in one bin loop over their own
-// system's slots; an exhausted or idle lane contributes zero.
+// system's slots; an exhausted or idle lane contributes zero.  Systems may
+// take different iteration counts n: a bin iterates as often as its largest
+// n, and a system stops correcting (and keeps its last iterate) after its own.
 #include "hermite_coeffs.h"
 #include "kernels.h"
 #include "pair_chain.h"
@@ -23,11 +25,12 @@ struct LaneInfo {
     int lo, hi;    // slot range of that system inside the bin
     int maxlen;    // largest system in the bin
     int64_t g;     // global particle index
+    int maxiter;   // largest iteration count in the bin (with per-system counts)
 };
 
-__device__ __forceinline__ LaneInfo lane_info(const BatchPlan &pl, int b, int lane)
+__device__ __forceinline__ LaneInfo lane_info(const BatchPlan &pl, int b, int lane, const int *iters = nullptr)
 {
-    LaneInfo li{-1, lane, lane + 1, 0, 0};
+    LaneInfo li{-1, lane, lane + 1, 0, 0, 0};
     const int s0 = pl.bin_start[b], s1 = pl.bin_start[b + 1];
     int base = 0;
     for (int k = s0; k < s1; ++k) {
@@ -35,6 +38,7 @@ __device__ __forceinline__ LaneInfo lane_info(const BatchPlan &pl, int b, int la
         const int64_t off = pl.offsets[s];
         const int sz = (int)(pl.offsets[s + 1] - off);
         li.maxlen = max(li.maxlen, sz);
+        if (iters) li.maxiter = max(li.maxiter, iters[s]);
         if (lane >= base && lane < base + sz) {
             li.sys = s;
             li.lo = base;
@@ -104,7 +108,8 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                                                            double *__restrict__ pos, double *__restrict__ vel,
                                                            double *__restrict__ deriv,
                                                            const double *__restrict__ dt_sys, int n_steps,
-                                                           int n_iter, double G, double eps2)
+                                                           int n_iter, const int *__restrict__ iters, double G,
+                                                           double eps2)
 {
     constexpr int K = P;
     __shared__ double sm[kLanes];
@@ -121,8 +126,12 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
         const int b = next_bin;
         __syncthreads();
         if (b >= pl.n_bins) break;
-        const LaneInfo li = lane_info(pl, b, lane);
+        const LaneInfo li = lane_info(pl, b, lane, iters);
         const bool active = li.sys >= 0;
+        // iterations of this bin and of this lane's system (the host checks
+        // every count is in 1..64)
+        const int bin_iter = iters ? li.maxiter : n_iter;
+        const int my_iter = (iters && active) ? iters[li.sys] : bin_iter;
 
         double x[3], v[3], d[2 * P][3];
         double dt = 1.0;
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             }
             double a1[K + 1][3];
             double x1[3], v1[3];
-            for (int it = 0; it < n_iter; ++it) {
+            for (int it = 0; it < bin_iter; ++it) {
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
@@ -222,6 +231,8 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         chain_accumulate<K, float>(r, vv, aa, jj, m * rinv * rinv2, rinv2, accf);
                     }
                 }
+                // a system past its own iteration count keeps its last iterate
+                if (it >= my_iter) continue;
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                     dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1[c] + v[c]));
                     x1[c] = __builtin_fma(dx, dt, x[c]);
                 }
-                if (it + 1 < n_iter) {
+                if (it + 1 < my_iter) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         path[0][c] = x1[c];
@@ -295,14 +306,14 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
 
 template <int P, bool MIXED>
 hipError_t run_pm(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
-                  double *deriv, const double *dt_sys, int n_steps, int n_iter, double G, double eps2, int wg,
-                  hipStream_t st)
+                  double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
+                  double eps2, int wg, hipStream_t st)
 {
     const dim3 g(wg), b(kLanes);
     switch (corrector) {
-        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, G, eps2); break;
-        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, G, eps2); break;
-        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, G, eps2); break;
+        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
+        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
+        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -343,16 +354,16 @@ hipError_t launch_batch_init(const BatchPlan &pl, int p, int64_t n, const double
 
 hipError_t launch_batch_run(const BatchPlan &pl, int p, bool mixed, int corrector, int64_t n, const double *mass,
                             double *pos, double *vel, double *deriv, const double *dt_sys, int n_steps, int n_iter,
-                            double G, double eps2, int n_workgroups, hipStream_t st)
+                            const int *iters, double G, double eps2, int n_workgroups, hipStream_t st)
 {
     if (pl.n_bins <= 0 || n <= 0 || n_steps <= 0) return hipSuccess;
     if (n_workgroups < 1) n_workgroups = 1;
 #define HERMITE_BATCH_CASE(PP)                                                                                     \
     case PP:                                                                                                       \
-        return mixed ? run_pm<PP, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, G, eps2, \
-                                        n_workgroups, st)                                                          \
-                     : run_pm<PP, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, G,      \
-                                         eps2, n_workgroups, st);
+        return mixed ? run_pm<PP, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,   \
+                                        G, eps2, n_workgroups, st)                                                 \
+                     : run_pm<PP, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,  \
+                                         G, eps2, n_workgroups, st);
     switch (p) {
         HERMITE_BATCH_CASE(1)
         HERMITE_BATCH_CASE(2)

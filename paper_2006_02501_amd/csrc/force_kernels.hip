@@ -20,7 +20,7 @@
 // sums); Split (a and adot as in FP64, a^(2) and a^(3) as in Mixed, from the
 // same FP64 differences); Generic (the FP64 recurrence up to the 5th
 // derivative, for the initialisation).
-#include "kernels.h"
+#include "force_launch.h"
 #include "pair_chain.h"
 
 namespace hermite {

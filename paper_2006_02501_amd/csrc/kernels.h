@@ -1,50 +1,13 @@
-// Internal launcher declarations shared by the runtime and the kernel files.
+// Internal launcher declarations shared by the runtime and the kernel files
+// (the evaluation's own are in force_launch.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "force_launch.h"
+
 namespace hermite {
-
-constexpr int kBlock = 256;   // threads per workgroup of the tiled evaluation (4 wave64)
-constexpr int kTile = 256;    // j-particles staged in LDS per tile
-constexpr int kMaxPath = 6;   // path derivatives x^(0..5) (generic initialisation)
-
-enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2, Split = 3 };
-
-// Where the evaluation reads the j-particles from: LDS tiles filled by the
-// workgroup, or packed records streamed through the scalar unit into SGPRs.
-enum class JSource { Lds = 0, Scalar = 1 };
-
-struct ForceArgs {
-    int64_t n;                    // particles (i and j range over all of them)
-    const double *mass;           // [n]
-    const double *path[kMaxPath]; // path[k] = [3][n] block of x^(k)
-    int K;                        // highest derivative evaluated
-    int k_first;                  // first derivative written (outputs k_first..K)
-    double G, eps2;
-    double *out;                  // [K+1-k_first][3][n]
-    double *partial;              // split partial sums [nsplit][K+1-k_first][3][n]
-    int64_t partial_cap;          // capacity of partial, in doubles
-    double *jrec;                 // packed j-records [n][16] (scalar source)
-};
-
-// Launch shape of the FP64 / mixed evaluation (the generic initialisation
-// chain always uses 4-wave workgroups with one i-particle per lane).
-struct LaunchShape {
-    int ipt;          // i-particles per lane: 1 or 2
-    int waves;        // waves per workgroup: 4 or 16 (16 with ipt = 1 only)
-    JSource jsource;  // LDS tiles or scalar stream
-};
-
-// Doubles per particle of the packed j-stream.
-constexpr int kJRecDoubles = 16;
-
-// Evaluates with the given chain, launch shape and j-split count.
-hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &shape, int nsplit, hipStream_t st);
-
-// j-split count the evaluation uses when the caller does not fix one.
-int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 
 // Predictor and corrector take dt from dt_dev[0] when dt_dev is not null.
 hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, const double *pos, const double *vel,
@@ -84,9 +47,12 @@ struct BatchPlan {
 hipError_t launch_batch_init(const BatchPlan &plan, int p, int64_t n, const double *mass, const double *pos,
                              const double *vel, double *deriv, double G, double eps2, hipStream_t st);
 
+// iters: per-system iteration counts (device, [n_sys], each 1..64) or null
+// for n_iter everywhere.
 hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int corrector, int64_t n,
                             const double *mass, double *pos, double *vel, double *deriv, const double *dt_sys,
-                            int n_steps, int n_iter, double G, double eps2, int n_workgroups, hipStream_t st);
+                            int n_steps, int n_iter, const int *iters, double G, double eps2, int n_workgroups,
+                            hipStream_t st);
 
 hipError_t launch_reset_counter(int *counter, hipStream_t st);
 

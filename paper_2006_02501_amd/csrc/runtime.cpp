@@ -47,6 +47,7 @@ struct hermite_ctx {
     int32_t *d_bin_sys = nullptr;
     int64_t *d_offsets = nullptr;
     int *d_counter = nullptr;
+    int32_t *d_iters = nullptr;   // per-system iteration counts [n_sys]
     int batch_workgroups = 0;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -55,10 +56,12 @@ struct hermite_ctx {
         const double *mass, *dt;
         double *pos, *vel, *deriv;
         int n_steps, n_iter, workgroups;
+        bool per_system;
         bool operator==(const Key &o) const
         {
             return mass == o.mass && dt == o.dt && pos == o.pos && vel == o.vel && deriv == o.deriv &&
-                   n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups;
+                   n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups &&
+                   per_system == o.per_system;
         }
     } key{};
 };
@@ -206,6 +209,7 @@ void free_ctx(hermite_ctx *ctx)
     if (ctx->d_bin_sys) (void)hipFree(ctx->d_bin_sys);
     if (ctx->d_offsets) (void)hipFree(ctx->d_offsets);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->d_iters) (void)hipFree(ctx->d_iters);
     if (ctx->jrec) (void)hipFree(ctx->jrec);
     if (ctx->qpart) (void)hipFree(ctx->qpart);
     if (ctx->vs) (void)hipFree(ctx->vs);
@@ -607,6 +611,7 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
                          bin_sys.size() * sizeof(int32_t)) &&
               alloc_copy((void **)&ctx->d_offsets, ctx->offsets.data(), ctx->offsets.size() * sizeof(int64_t)) &&
               alloc_copy((void **)&ctx->d_counter, nullptr, sizeof(int)) &&
+              alloc_copy((void **)&ctx->d_iters, nullptr, (size_t)n_sys * sizeof(int32_t)) &&
               alloc_copy((void **)&ctx->flag, nullptr, sizeof(int));
     if (!ok) {
         free_ctx(ctx);
@@ -646,21 +651,35 @@ hermite_status hermite_batch_init(hermite_ctx *ctx, hermite_state *s)
     return HERMITE_OK;
 }
 
-hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
-                                 int32_t n_iter)
+static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                     int32_t n_iter, const int32_t *iters_host)
 {
     if (!ctx) return HERMITE_E_ARG;
     if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
-    if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
     if (n_steps < 0) return fail(ctx, HERMITE_E_ARG, "hermite: n_steps must be >= 0");
+    if (iters_host) {
+        n_iter = 1;
+        for (int32_t i = 0; i < ctx->n_sys; ++i) {
+            if (iters_host[i] < 1 || iters_host[i] > 64)
+                return fail(ctx, HERMITE_E_ARG, "hermite: every per-system n_iter must be in 1..64");
+            n_iter = std::max(n_iter, iters_host[i]);
+        }
+    } else if (n_iter < 1) {
+        return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
+    }
     hermite_status st = check_state(ctx, s, true, false);
     if (st != HERMITE_OK) return st;
     if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the batch total");
     if (ctx->n_sys > 0 && !dt_sys) return fail(ctx, HERMITE_E_ARG, "hermite: dt_sys is NULL");
     if (n_steps == 0 || ctx->n_sys == 0) return HERMITE_OK;
+    if (iters_host)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_iters, iters_host, (size_t)ctx->n_sys * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, ctx->stream),
+                "per-system n_iter copy");
     int wg = ctx->batch_workgroups;
     if (wg <= 0) wg = std::min<int>(ctx->n_bins, 256 * 8);
-    hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, n_steps, n_iter, wg};
+    const bool per_system = iters_host != nullptr;
+    hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, n_steps, per_system ? 0 : n_iter, wg, per_system};
     if (!ctx->graph_exec || !(key == ctx->key)) {
         if (ctx->graph_exec) { (void)hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
         if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
@@ -669,7 +688,8 @@ hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const doubl
         hipError_t e1 = hermite::launch_reset_counter(ctx->d_counter, cs);
         hipError_t e2 = hermite::launch_batch_run(plan_of(ctx), ctx->p, ctx->prm.precision == HERMITE_MIXED,
                                                   ctx->prm.corrector, s->n, s->mass, s->pos, s->vel, s->deriv,
-                                                  dt_sys, n_steps, n_iter, ctx->prm.G, ctx->prm.eps2, wg, cs);
+                                                  dt_sys, n_steps, n_iter, per_system ? ctx->d_iters : nullptr,
+                                                  ctx->prm.G, ctx->prm.eps2, wg, cs);
         hipGraph_t g = nullptr;
         hipError_t e3 = hipStreamEndCapture(cs, &g);
         if (e1 != hipSuccess) return hip_fail(ctx, e1, "graph capture (counter reset)");
@@ -685,6 +705,19 @@ hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const doubl
     const double *arrs[3] = {s->pos, s->vel, s->deriv};
     const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
     return check_finite(ctx, arrs, cnt, 3);
+}
+
+hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                 int32_t n_iter)
+{
+    return batch_run_impl(ctx, s, dt_sys, n_steps, n_iter, nullptr);
+}
+
+hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                       const int32_t *n_iter_sys)
+{
+    if (ctx && ctx->n_sys > 0 && !n_iter_sys) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter_sys is NULL");
+    return batch_run_impl(ctx, s, dt_sys, n_steps, 0, n_iter_sys ? n_iter_sys : nullptr);
 }
 
 }  // extern "C"

@@ -61,6 +61,8 @@ _SIGS = {
                                             _P, ctypes.POINTER(_P)]),
     "hermite_batch_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
     "hermite_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]),
+    "hermite_batch_run_iters": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32)]),
     "hermite_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hermite_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -280,13 +282,27 @@ class BatchHermite:
     def init(self, st):
         _check(self.ctx, self.lib.hermite_batch_init(self.ctx, ctypes.byref(st.c)))
 
-    def run(self, st, dt_sys, n_steps, n_iter):
+    def _dt_tensor(self, dt_sys):
         if not isinstance(dt_sys, torch.Tensor):
             dt_sys = torch.as_tensor(np.asarray(dt_sys, dtype=np.float64))
         dt_sys = dt_sys.to(device=self.device, dtype=torch.float64).contiguous()
         self._dt = dt_sys          # keep alive: the captured graph holds its address
-        _check(self.ctx, self.lib.hermite_batch_run(self.ctx, ctypes.byref(st.c), ctypes.c_void_p(dt_sys.data_ptr()),
-                                                    int(n_steps), int(n_iter)))
+        return dt_sys
+
+    def run(self, st, dt_sys, n_steps, n_iter):
+        """n_iter: one count for every system, or a sequence of one per system."""
+        dt_sys = self._dt_tensor(dt_sys)
+        if np.ndim(n_iter) == 0:
+            _check(self.ctx, self.lib.hermite_batch_run(self.ctx, ctypes.byref(st.c),
+                                                        ctypes.c_void_p(dt_sys.data_ptr()), int(n_steps),
+                                                        int(n_iter)))
+        else:
+            it = np.ascontiguousarray(n_iter, dtype=np.int32)
+            if it.shape != (self.n_sys,):
+                raise ValueError("one n_iter per system")
+            _check(self.ctx, self.lib.hermite_batch_run_iters(
+                self.ctx, ctypes.byref(st.c), ctypes.c_void_p(dt_sys.data_ptr()), int(n_steps),
+                it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return dt_sys
 
 
