@@ -357,6 +357,53 @@ def fig4_sweep(orbits=2000, chunks=20):
     return out
 
 
+def table1(chunk=200000, etas=(0.08, 0.04, 0.02, 0.01, 0.005), iters=(3, 4), t_end=100 * np.pi):
+    """The N-body test of Sec. 3.3 (Table 1): the 100-body disc, 8th order,
+    variable time-symmetric steps (Eq. 25), n = 3 and 4 for every eta, plus
+    the 4th-order run at n = 4, eta = 0.08; each run one system of the
+    ensemble form (one workgroup each, all in one launch per order), to
+    t = 100 pi; the statistic is the median |E/E0 - 1| over the last time
+    unit."""
+    import torch
+    from paper_2006_02501_amd import EnsembleHermite
+    from workloads import disc100
+
+    w = disc100()
+    n1 = len(w["mass"])
+    out = {"t_end": t_end, "eps": 1e-6, "runs": []}
+    t0 = time.perf_counter()
+    for order, grid in ((8, [(n, e) for n in iters for e in etas]), (4, [(4, 0.08)])):
+        k = len(grid)
+        mass = np.tile(w["mass"], k)
+        x = np.ascontiguousarray(np.tile(w["x"], (1, k)))
+        v = np.ascontiguousarray(np.tile(w["v"], (1, k)))
+        off = np.arange(0, n1 * (k + 1), n1, dtype=np.int64)
+        eh = EnsembleHermite(order, off, eps2=w["eps2"], device="cuda:0")
+        st = eh.state(mass, x, v)
+        eh.init(st, rec_cap=40000)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        gpu_ms = 0.0
+        while True:
+            ev0.record()
+            res = eh.run(st, [e for _, e in grid], t_end, [n for n, _ in grid], rec_from=t_end - 1.0,
+                         max_steps=chunk)
+            ev1.record()
+            torch.cuda.synchronize()
+            gpu_ms += ev0.elapsed_time(ev1)
+            log("    table1 order %d: t = %s" % (order, ", ".join("%.1f" % r["t"] for r in res)))
+            if all(r["t"] >= t_end for r in res):
+                break
+        for i, ((n, e), r) in enumerate(zip(grid, res)):
+            rec = eh.records(i, r["records"])
+            dE = np.abs(rec[:, 1] / r["E0"] - 1.0)
+            out["runs"].append({"order": order, "n_iter": n, "eta": e, "median_dE_last_unit": float(np.median(dE)),
+                                "steps": r["steps"], "records": r["records"], "rec_overflow": r["rec_overflow"]})
+        out["gpu_s_order%d" % order] = gpu_ms / 1e3
+        eh.close()
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def calibrate_copy(mib=256, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -382,6 +429,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variable-step", action="store_true")
     ap.add_argument("--no-fig4", action="store_true", help="skip the 2000-orbit iteration-count sweep")
+    ap.add_argument("--table1", action="store_true",
+                    help="also run the Sec. 3.3 N-body test grid (Table 1) to t = 100 pi (a few minutes)")
+    ap.add_argument("--table1-only", action="store_true", help="run only the Table 1 grid")
+    ap.add_argument("--table1-etas", default="0.08,0.04,0.02,0.01,0.005")
+    ap.add_argument("--table1-iters", default="3,4", help="iteration counts of the 8th-order rows")
     ap.add_argument("--eta", type=float, default=0.4,
                     help="variable-step accuracy parameter (0.4 gives dt near 2 pi / 2000 on this disc)")
     ap.add_argument("--no-per-system", action="store_true",
@@ -396,6 +448,12 @@ def main():
         sys.exit(2)
     import torch  # noqa: F401
     from workloads import disc16k
+
+    if args.table1_only:
+        etas = tuple(float(e) for e in args.table1_etas.split(","))
+        iters = tuple(int(q) for q in args.table1_iters.split(","))
+        print(json.dumps({"table1": table1(etas=etas, iters=iters)}), flush=True)
+        return
 
     calib = calibrate_copy() if args.calibrate_copy else None
     w = disc16k()
@@ -468,6 +526,10 @@ def main():
         log("  batched ...")
         out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)
         log("  batched: %s" % json.dumps({k: out["batched"][k] for k in ("fp64", "mixed")}))
+    if args.table1:
+        log("  table 1 ...")
+        out["table1"] = table1(etas=tuple(float(e) for e in args.table1_etas.split(",")),
+                               iters=tuple(int(q) for q in args.table1_iters.split(",")))
     if not args.no_cpu_baseline:
         log("  cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -234,6 +234,53 @@ hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const
                                        int32_t n_steps, const int32_t *n_iter_sys);
 
 /*
+ * Ensemble form (Sec. 3.3 N-body test, Table 1): n_sys independent systems of
+ * 2..128 bodies (offsets as for the batched form, HOST array), FP64, each
+ * integrated by one workgroup with the variable time-symmetric step (the
+ * criterion and step rule of hermite_step_symmetric, forwards) for many
+ * steps inside one launch.  Every system keeps its own time on the device,
+ * starting at 0 at hermite_ensemble_init.
+ *
+ * hermite_ensemble_create: params must have precision HERMITE_FP64 and
+ * compensated 0; systems outside 2..128 bodies -> E_ARG.
+ * hermite_ensemble_init: initial derivatives of every system (as
+ * hermite_init), system times, step and record counts reset to 0.
+ * hermite_ensemble_run: cfg is a HOST array [n_sys]; each system takes steps
+ * until its time reaches cfg.t_end or this call has taken max_steps steps of
+ * it.  After every step that ends at t > cfg.rec_from the system's energy
+ *   E = sum_i m_i v_i^2 / 2 - sum_{i<j} G m_i m_j (r_ij^2 + eps^2)^(-1/2)
+ * is recorded as (t, E) at rec[(sys * rec_cap + k) * 2] (DEVICE buffer, k
+ * counting on across calls; beyond rec_cap records are dropped and
+ * rec_overflow is set).  E at time 0 is in res.E0.  res (HOST [n_sys])
+ * receives every system's time, E0, cumulative steps and records, and flags.
+ * Synchronises.  E_NONFINITE if a system's criterion became undefined (its
+ * res.failed is 1 and it takes no further steps).
+ */
+typedef struct {
+    double eta;        /* Eq. 25 accuracy parameter, finite and > 0              */
+    double t_end;      /* integrate until the system's time reaches t_end       */
+    double rec_from;   /* record (t, E) after every step ending past this time  */
+    int32_t n_iter;    /* P(EC)^n iterations, 1..64                             */
+    int32_t reserved;
+} hermite_vstep_cfg;
+
+typedef struct {
+    double t;          /* the system's time                                     */
+    double E0;         /* its energy at time 0                                  */
+    int64_t steps;     /* steps taken since hermite_ensemble_init               */
+    int32_t records;   /* records written                                       */
+    int32_t failed;    /* 1: the criterion became undefined                     */
+    int32_t rec_overflow;
+    int32_t reserved;
+} hermite_vstep_result;
+
+hermite_status hermite_ensemble_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
+                                       void *hip_stream, hermite_ctx **out);
+hermite_status hermite_ensemble_init(hermite_ctx *ctx, hermite_state *s);
+hermite_status hermite_ensemble_run(hermite_ctx *ctx, hermite_state *s, const hermite_vstep_cfg *cfg,
+                                    int64_t max_steps, int32_t rec_cap, double *rec, hermite_vstep_result *res);
+
+/*
  * Launch-shape tuning for hermite_force_derivs.
  *   i_per_thread   1 or 2 i-particles per lane
  *   j_split        number of j-ranges summed by separate workgroups (0 = auto,

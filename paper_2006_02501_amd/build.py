@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhermite.so")
-SOURCES = ["force_kernels.hip", "step_kernels.hip", "timestep_kernels.hip", "batch_kernel.hip", "runtime.cpp"]
+SOURCES = ["force_kernels.hip", "step_kernels.hip", "timestep_kernels.hip", "batch_kernel.hip",
+           "ensemble_kernels.hip", "runtime.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,7 +40,7 @@ def _compile(src):
 def build(verbose=False):
     """Compile every HIP source and link the shared library (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:

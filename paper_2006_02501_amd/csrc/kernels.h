@@ -56,4 +56,41 @@ hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int correc
 
 hipError_t launch_reset_counter(int *counter, hipStream_t st);
 
+// Ensemble form (systems of 2..128 bodies, one workgroup each, variable
+// time-symmetric steps on the device) -------------------------------------
+struct Path6Ptr {
+    const double *p[6];
+};
+
+// Per-system run settings and running status; their layouts are those of
+// hermite_vstep_cfg and hermite_vstep_result in hermite.h.
+struct EnsembleCfg {
+    double eta, t_end, rec_from;
+    int32_t n_iter, reserved;
+};
+struct EnsembleStatus {
+    double t, E0;
+    int64_t steps;
+    int32_t records, failed, rec_overflow, reserved;
+};
+
+struct EnsembleArgs {
+    int32_t n_sys;
+    int64_t n;                  // bodies over all systems
+    const int64_t *offsets;     // [n_sys+1] (device)
+    const double *mass;
+    double *pos, *vel, *deriv;
+    double G, eps2;
+    const EnsembleCfg *cfg;     // [n_sys] (device)
+    EnsembleStatus *status;     // [n_sys] (device)
+    double *rec;                // [n_sys][rec_cap][2] (t, E) (device)
+    int32_t rec_cap;
+    int64_t max_steps;          // per system and launch
+};
+
+hipError_t launch_ensemble_init(const int64_t *offsets, int32_t n_sys, int p, int64_t n, const double *mass,
+                                const double *pos, const double *vel, double *deriv, double G, double eps2,
+                                hipStream_t st);
+hipError_t launch_ensemble_run(const EnsembleArgs &a, int p, int corrector, hipStream_t st);
+
 }  // namespace hermite

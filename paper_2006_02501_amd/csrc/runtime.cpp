@@ -48,6 +48,10 @@ struct hermite_ctx {
     int64_t *d_offsets = nullptr;
     int *d_counter = nullptr;
     int32_t *d_iters = nullptr;   // per-system iteration counts [n_sys]
+    // ensemble form
+    bool ensemble = false;
+    hermite::EnsembleCfg *d_cfg = nullptr;
+    hermite::EnsembleStatus *d_status = nullptr;
     int batch_workgroups = 0;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -210,6 +214,8 @@ void free_ctx(hermite_ctx *ctx)
     if (ctx->d_offsets) (void)hipFree(ctx->d_offsets);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     if (ctx->d_iters) (void)hipFree(ctx->d_iters);
+    if (ctx->d_cfg) (void)hipFree(ctx->d_cfg);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->jrec) (void)hipFree(ctx->jrec);
     if (ctx->qpart) (void)hipFree(ctx->qpart);
     if (ctx->vs) (void)hipFree(ctx->vs);
@@ -295,7 +301,8 @@ hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_
 hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context, use hermite_batch_init");
+    if (ctx->batch || ctx->ensemble)
+        return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context, use its own init");
     hermite_status st = check_state(ctx, s, false, false);
     if (st != HERMITE_OK) return st;
     const int p = ctx->p;
@@ -329,6 +336,7 @@ hermite_status hermite_init(hermite_ctx *ctx, hermite_state *s)
 hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt)
 {
     if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
@@ -340,6 +348,7 @@ hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt)
 hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
 {
     if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     hermite_status st = check_state(ctx, s, false, true);
     if (st != HERMITE_OK) return st;
     const int p = ctx->p;
@@ -355,6 +364,7 @@ hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
 hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter)
 {
     if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
@@ -368,7 +378,8 @@ hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, in
 hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32_t n_iter)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context, use hermite_batch_run");
+    if (ctx->batch || ctx->ensemble)
+        return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context, use its own run call");
     if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
@@ -387,7 +398,7 @@ hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32
 hermite_status hermite_step_criterion(hermite_ctx *ctx, const hermite_state *s, double eta, double *h)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     hermite_status st = check_state(ctx, s, false, false);
     if (st != HERMITE_OK) return st;
     if (!h) return fail(ctx, HERMITE_E_ARG, "hermite: h is NULL");
@@ -411,7 +422,7 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
                                       double direction, double *dt_taken)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     if (n_iter < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be >= 1");
     if (!std::isfinite(eta) || !(eta > 0.0)) return fail(ctx, HERMITE_E_ARG, "hermite: eta must be finite and > 0");
     if (direction != 1.0 && direction != -1.0) return fail(ctx, HERMITE_E_ARG, "hermite: direction must be +1 or -1");
@@ -456,6 +467,7 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
 hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, double *phi)
 {
     if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     hermite_status st = check_state(ctx, s, false, false);
     if (st != HERMITE_OK) return st;
     if (s->n > 0 && !phi) return fail(ctx, HERMITE_E_ARG, "hermite: phi is NULL");
@@ -468,7 +480,7 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
                                 int32_t *j_source, int32_t *wg_waves)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: batched context");
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     hermite_status st = check_state(ctx, s, false, true);
     if (st != HERMITE_OK) return st;
     struct Cand {
@@ -705,6 +717,119 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
     const double *arrs[3] = {s->pos, s->vel, s->deriv};
     const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
     return check_finite(ctx, arrs, cnt, 3);
+}
+
+static_assert(sizeof(hermite_vstep_cfg) == sizeof(hermite::EnsembleCfg), "cfg layout");
+static_assert(sizeof(hermite_vstep_result) == sizeof(hermite::EnsembleStatus), "result layout");
+
+hermite_status hermite_ensemble_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
+                                       void *hip_stream, hermite_ctx **out)
+{
+    std::string msg;
+    if (!out) return HERMITE_E_ARG;
+    *out = nullptr;
+    hermite_status st = check_params(prm, msg);
+    if (st != HERMITE_OK) return st;
+    if (prm->precision != HERMITE_FP64 || prm->compensated) return HERMITE_E_ARG;
+    if (n_sys < 0 || (n_sys > 0 && !offsets)) return HERMITE_E_ARG;
+    if (n_sys > 0 && offsets[0] != 0) return HERMITE_E_ARG;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        const int64_t sz = offsets[i + 1] - offsets[i];
+        if (sz < 2 || sz > 128) return HERMITE_E_ARG;
+    }
+    hermite_ctx *ctx = new hermite_ctx();
+    ctx->prm = *prm;
+    ctx->p = prm->order / 2 - 1;
+    ctx->ensemble = true;
+    ctx->n_sys = n_sys;
+    ctx->offsets.assign(offsets, offsets + (n_sys + 1));
+    ctx->n_max = n_sys > 0 ? offsets[n_sys] : 0;
+    ctx->stream = (hipStream_t)hip_stream;
+    const size_t ns = (size_t)std::max(n_sys, 1);
+    bool ok = hipMalloc((void **)&ctx->d_offsets, (ns + 1) * sizeof(int64_t)) == hipSuccess &&
+              hipMalloc((void **)&ctx->d_cfg, ns * sizeof(hermite::EnsembleCfg)) == hipSuccess &&
+              hipMalloc((void **)&ctx->d_status, ns * sizeof(hermite::EnsembleStatus)) == hipSuccess &&
+              hipMalloc((void **)&ctx->flag, sizeof(int)) == hipSuccess;
+    if (ok && n_sys > 0)
+        ok = hipMemcpy(ctx->d_offsets, offsets, (size_t)(n_sys + 1) * sizeof(int64_t), hipMemcpyHostToDevice) ==
+             hipSuccess;
+    if (!ok) {
+        free_ctx(ctx);
+        return HERMITE_E_ALLOC;
+    }
+    *out = ctx;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_ensemble_init(hermite_ctx *ctx, hermite_state *s)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: not an ensemble context");
+    hermite_status st = check_state(ctx, s, false, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the ensemble total");
+    if (ctx->n_sys == 0) {
+        s->initialized = 1;
+        return HERMITE_OK;
+    }
+    HIP_TRY(ctx, hermite::launch_ensemble_init(ctx->d_offsets, ctx->n_sys, ctx->p, s->n, s->mass, s->pos, s->vel,
+                                               s->deriv, ctx->prm.G, ctx->prm.eps2, ctx->stream),
+            "ensemble init launch");
+    HIP_TRY(ctx, hipMemsetAsync(ctx->d_status, 0, (size_t)ctx->n_sys * sizeof(hermite::EnsembleStatus), ctx->stream),
+            "ensemble status clear");
+    s->initialized = 1;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_ensemble_run(hermite_ctx *ctx, hermite_state *s, const hermite_vstep_cfg *cfg,
+                                    int64_t max_steps, int32_t rec_cap, double *rec, hermite_vstep_result *res)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: not an ensemble context");
+    hermite_status st = check_state(ctx, s, true, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the ensemble total");
+    if (max_steps < 0) return fail(ctx, HERMITE_E_ARG, "hermite: max_steps must be >= 0");
+    if (rec_cap < 0 || (rec_cap > 0 && !rec)) return fail(ctx, HERMITE_E_ARG, "hermite: bad record buffer");
+    if (ctx->n_sys > 0 && (!cfg || !res)) return fail(ctx, HERMITE_E_ARG, "hermite: cfg and res are required");
+    for (int32_t i = 0; i < ctx->n_sys; ++i) {
+        const hermite_vstep_cfg &c = cfg[i];
+        if (!std::isfinite(c.eta) || !(c.eta > 0.0) || !std::isfinite(c.t_end) || std::isnan(c.rec_from) ||
+            c.n_iter < 1 || c.n_iter > 64)
+            return fail(ctx, HERMITE_E_ARG,
+                        "hermite: each system needs eta finite and > 0, t_end finite, rec_from not NaN, "
+                        "n_iter in 1..64");
+    }
+    if (ctx->n_sys == 0) return HERMITE_OK;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cfg, cfg, (size_t)ctx->n_sys * sizeof(hermite::EnsembleCfg),
+                                hipMemcpyHostToDevice, ctx->stream),
+            "ensemble cfg copy");
+    hermite::EnsembleArgs a{};
+    a.n_sys = ctx->n_sys;
+    a.n = s->n;
+    a.offsets = ctx->d_offsets;
+    a.mass = s->mass;
+    a.pos = s->pos;
+    a.vel = s->vel;
+    a.deriv = s->deriv;
+    a.G = ctx->prm.G;
+    a.eps2 = ctx->prm.eps2;
+    a.cfg = ctx->d_cfg;
+    a.status = ctx->d_status;
+    a.rec = rec;
+    a.rec_cap = rec_cap;
+    a.max_steps = max_steps;
+    if (max_steps > 0)
+        HIP_TRY(ctx, hermite::launch_ensemble_run(a, ctx->p, ctx->prm.corrector, ctx->stream), "ensemble run launch");
+    HIP_TRY(ctx, hipMemcpyAsync(res, ctx->d_status, (size_t)ctx->n_sys * sizeof(hermite::EnsembleStatus),
+                                hipMemcpyDeviceToHost, ctx->stream),
+            "ensemble status copy");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "ensemble sync");
+    for (int32_t i = 0; i < ctx->n_sys; ++i)
+        if (res[i].failed)
+            return fail(ctx, HERMITE_E_NONFINITE,
+                        "hermite: the step criterion became undefined in a system (see its result's failed flag)");
+    return HERMITE_OK;
 }
 
 hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,

@@ -39,6 +39,17 @@ class StateC(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("comp", ctypes.c_void_p), ("t_comp", ctypes.c_double)]
 
 
+class VstepCfg(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("t_end", ctypes.c_double), ("rec_from", ctypes.c_double),
+                ("n_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class VstepResult(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("E0", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("records", ctypes.c_int32), ("failed", ctypes.c_int32), ("rec_overflow", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes); mirrors include/hermite.h
@@ -63,6 +74,11 @@ _SIGS = {
     "hermite_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]),
     "hermite_batch_run_iters": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32,
                                                ctypes.POINTER(ctypes.c_int32)]),
+    "hermite_ensemble_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int64), _P, ctypes.POINTER(_P)]),
+    "hermite_ensemble_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
+    "hermite_ensemble_run": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(VstepCfg), ctypes.c_int64,
+                                            ctypes.c_int32, _P, ctypes.POINTER(VstepResult)]),
     "hermite_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hermite_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -304,6 +320,65 @@ class BatchHermite:
                 self.ctx, ctypes.byref(st.c), ctypes.c_void_p(dt_sys.data_ptr()), int(n_steps),
                 it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return dt_sys
+
+
+class EnsembleHermite:
+    """Ensemble form: independent systems of 2..128 bodies, each run by one
+    workgroup with the variable time-symmetric step, many steps per launch."""
+
+    def __init__(self, order, offsets, corrector="modified", G=1.0, eps2=0.0, device="cuda:0"):
+        self.lib = load_library()
+        self.order = order
+        self.p = order // 2 - 1
+        self.device = torch.device(device)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.n_sys = self.offsets.shape[0] - 1
+        self.prm = Params(order, 0, CORRECTORS[corrector], 0, float(G), float(eps2), 0, 0)
+        self.ctx = ctypes.c_void_p()
+        self.rec = None
+        _check(None, self.lib.hermite_ensemble_create(
+            ctypes.byref(self.prm), int(self.n_sys), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            _stream_handle(self.device), ctypes.byref(self.ctx)))
+
+    def close(self):
+        if self.ctx:
+            self.lib.hermite_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self, mass, x, v):
+        return DeviceState(self.p, mass, x, v, self.device, with_pred=False)
+
+    def init(self, st, rec_cap=0):
+        """Initial derivatives; system times and counters back to 0; a fresh
+        (t, E) record buffer of rec_cap entries per system."""
+        _check(self.ctx, self.lib.hermite_ensemble_init(self.ctx, ctypes.byref(st.c)))
+        self.rec_cap = int(rec_cap)
+        self.rec = torch.zeros((max(self.n_sys, 1), max(self.rec_cap, 1), 2), dtype=torch.float64,
+                               device=self.device)
+
+    def run(self, st, eta, t_end, n_iter, rec_from=float("inf"), max_steps=1 << 40):
+        """Per-system (or scalar) eta, t_end, n_iter, rec_from.  Returns a list
+        of dicts (t, E0, steps, records, failed, rec_overflow)."""
+        cfg = (VstepCfg * max(self.n_sys, 1))()
+        b = lambda q: np.broadcast_to(np.asarray(q), (self.n_sys,))
+        for i, (e, te, ni, rf) in enumerate(zip(b(eta), b(t_end), b(n_iter), b(rec_from))):
+            cfg[i] = VstepCfg(float(e), float(te), float(rf), int(ni), 0)
+        res = (VstepResult * max(self.n_sys, 1))()
+        _check(self.ctx, self.lib.hermite_ensemble_run(self.ctx, ctypes.byref(st.c), cfg, int(max_steps),
+                                                       self.rec_cap, ctypes.c_void_p(self.rec.data_ptr()), res))
+        return [dict(t=r.t, E0=r.E0, steps=r.steps, records=r.records, failed=r.failed,
+                     rec_overflow=r.rec_overflow) for r in res[: self.n_sys]]
+
+    def records(self, sys, count=None):
+        """(t, E) records of one system as a numpy array [count][2]."""
+        r = self.rec[sys].cpu().numpy()
+        return r if count is None else r[:count]
 
 
 def version():
