@@ -62,10 +62,50 @@ constexpr int64_t iblock_size(int w, bool share, int ipt) { return (int64_t)(sha
 template <int K>
 constexpr int row_stride() { return ((1 + 3 * (K + 1)) + 1) & ~1; }
 
-template <int K, Chain CH, int IPT, bool DIAG, int UNROLL = 2>
+// Running maximum, per i-particle, of the pair rate G (m_i + m_j) / (r^2 +
+// eps^2)^(3/2) that sets the variable step of Sec. 3.3 (Eq. 25), taken along
+// with the evaluation when QM (FP64 and split chains: one multiply, one FMA
+// and one max per pair on the FP64 1/r they already have).
+template <bool QM, int IPT>
+struct RateMax {
+    double gm[IPT];   // G m_i
+    double q[IPT];
+    __device__ __forceinline__ void add(int k, double mr3, double r3)
+    {
+        if constexpr (QM) q[k] = __builtin_fmax(q[k], __builtin_fma(gm[k], r3, mr3));
+    }
+};
+
+// Largest rate over a workgroup of W waves (lanes past n give 0); thread 0
+// writes it to qpart[blockIdx.y * gridDim.x + blockIdx.x].
+template <bool QM, int IPT, int W>
+__device__ __forceinline__ void store_rate(const RateMax<QM, IPT> &rm, const int64_t (&ii)[IPT], int64_t n,
+                                           double *__restrict__ qpart)
+{
+    if constexpr (QM) {
+        __shared__ double wq[W];
+        double q = 0.0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) q = ii[k] < n ? __builtin_fmax(q, rm.q[k]) : q;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) q = __builtin_fmax(q, __shfl_xor(q, off, 64));
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) wq[threadIdx.x >> 6] = q;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = wq[0];
+#pragma unroll
+            for (int w = 1; w < W; ++w) r = __builtin_fmax(r, wq[w]);
+            qpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = r;
+        }
+    }
+}
+
+template <int K, Chain CH, int IPT, bool DIAG, bool QM, int UNROLL = 2>
 __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const float *__restrict__ mtile, int cnt,
                                           int64_t j0, const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
-                                          double eps2, double (&acc)[IPT][K + 1][3], float (&accf)[IPT][K + 1][3])
+                                          double eps2, double (&acc)[IPT][K + 1][3], float (&accf)[IPT][K + 1][3],
+                                          RateMax<QM, IPT> &rm)
 {
     constexpr int RS = row_stride<K>();
 #pragma unroll UNROLL
@@ -92,6 +132,7 @@ __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const
                 const double rinv = rsqrt64(w);
                 const double rinv2 = rinv * rinv;
                 const double mr3 = m * rinv * rinv2;
+                if constexpr (QM) rm.add(q, mr3, (DIAG && self) ? 0.0 : rinv * rinv2);
                 chain_accumulate<K, double>(r, v, a, j, mr3, rinv2, acc[q]);
             } else if constexpr (CH == Chain::Mixed) {
                 float r[3], v[3], a[3], j[3];
@@ -131,6 +172,7 @@ __device__ __forceinline__ void tile_pass(const double *__restrict__ tile, const
                 const double rinv = rsqrt64(w);
                 const double rinv2 = rinv * rinv;
                 const double mr3 = m * rinv * rinv2;
+                if constexpr (QM) rm.add(q, mr3, (DIAG && self) ? 0.0 : rinv * rinv2);
                 chain_split<K>(r, v, a, j, mr3, rinv2, acc[q], accf[q]);
             } else {
                 double r[K + 1][3];
@@ -177,10 +219,10 @@ __device__ __forceinline__ void reduce_waves(double *buf, int wave, int lane, do
 // i-particles and each takes its 64-row slice of every j-tile (their sums are
 // added through LDS at the end); otherwise every lane has its own i-particles.
 // A j-tile has 64*W rows, one loaded by each thread.
-template <int K, Chain CH, int IPT, int W, bool SHARE>
+template <int K, Chain CH, int IPT, int W, bool SHARE, bool QM>
 __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
                                                           double G, double eps2, int64_t j_chunk, int k_first,
-                                                          double *__restrict__ out)
+                                                          double *__restrict__ out, double *__restrict__ qpart)
 {
     constexpr int RS = row_stride<K>();
     constexpr int UNR = 2;
@@ -203,10 +245,15 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
     double xi[IPT][K + 1][3];
     double acc[IPT][K + 1][3];
     float accf[IPT][K + 1][3];
+    RateMax<QM, IPT> rm;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
         const bool ok = ii[q] < n;
+        if constexpr (QM) {
+            rm.gm[q] = ok ? G * mass[ii[q]] : 0.0;
+            rm.q[q] = 0.0;
+        }
 #pragma unroll
         for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -239,9 +286,11 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
         if constexpr (!folds<CH>()) {
             if (r1 > r0) {
                 if (diag)
-                    tile_pass<K, CH, IPT, true, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, true, QM, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc,
+                                                         accf, rm);
                 else
-                    tile_pass<K, CH, IPT, false, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, false, QM, UNR>(tile + r0 * RS, mtile, r1 - r0, j0 + r0, ii, xi, eps2, acc,
+                                                          accf, rm);
             }
         } else {
             // FP32 partial sums over kFold j at a time, folded into FP64: bounds
@@ -249,14 +298,17 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
             for (int s0 = r0; s0 < r1; s0 += kFold) {
                 const int cs = min(kFold, r1 - s0);
                 if (diag)
-                    tile_pass<K, CH, IPT, true, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, true, QM, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc,
+                                                         accf, rm);
                 else
-                    tile_pass<K, CH, IPT, false, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc, accf);
+                    tile_pass<K, CH, IPT, false, QM, UNR>(tile + s0 * RS, mtile + s0, cs, j0 + s0, ii, xi, eps2, acc,
+                                                          accf, rm);
                 fold_partials<K, CH, IPT>(acc, accf);
             }
         }
     }
 
+    store_rate<QM, IPT, W>(rm, ii, n, qpart);
     if constexpr (SHARE) {
         reduce_waves<K, IPT, W>(smem, wave, lane, acc);
         if (wave != 0) return;
@@ -305,11 +357,11 @@ __global__ __launch_bounds__(kBlock) void pack_j_kernel(int64_t n, const double 
     for (int e = 0; e < kJRec; ++e) dst[e] = rec[e];
 }
 
-template <int K, Chain CH, int IPT, bool DIAG>
+template <int K, Chain CH, int IPT, bool DIAG, bool QM>
 __device__ __forceinline__ void stream_range(const double *__restrict__ jrec, int64_t jb, int64_t je,
                                              const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
                                              double eps2, double (&acc)[IPT][K + 1][3],
-                                             float (&accf)[IPT][K + 1][3])
+                                             float (&accf)[IPT][K + 1][3], RateMax<QM, IPT> &rm)
 {
     if (jb >= je) return;
     constexpr int NJ = 1 + 3 * (K + 1);
@@ -349,6 +401,7 @@ __device__ __forceinline__ void stream_range(const double *__restrict__ jrec, in
                 }
                 const double rinv = rsqrt64(w);
                 const double rinv2 = rinv * rinv;
+                if constexpr (QM) rm.add(q, m * rinv * rinv2, (DIAG && self) ? 0.0 : rinv * rinv2);
                 chain_accumulate<K, double>(r, v, a, jk, m * rinv * rinv2, rinv2, acc[q]);
             } else if constexpr (CH == Chain::Split) {
                 double r[3], v[3];
@@ -368,6 +421,7 @@ __device__ __forceinline__ void stream_range(const double *__restrict__ jrec, in
                 }
                 const double rinv = rsqrt64(w);
                 const double rinv2 = rinv * rinv;
+                if constexpr (QM) rm.add(q, m * rinv * rinv2, (DIAG && self) ? 0.0 : rinv * rinv2);
                 chain_split<K>(r, v, a, jk, m * rinv * rinv2, rinv2, acc[q], accf[q]);
             } else {
                 float r[3], v[3], a[3], jk[3];
@@ -392,18 +446,18 @@ __device__ __forceinline__ void stream_range(const double *__restrict__ jrec, in
     }
 }
 
-template <int K, Chain CH, int IPT, bool DIAG>
+template <int K, Chain CH, int IPT, bool DIAG, bool QM>
 __device__ __forceinline__ void stream_folded(const double *__restrict__ jrec, int64_t jb, int64_t je,
                                               const int64_t (&ii)[IPT], const double (&xi)[IPT][K + 1][3],
                                               double eps2, double (&acc)[IPT][K + 1][3],
-                                              float (&accf)[IPT][K + 1][3])
+                                              float (&accf)[IPT][K + 1][3], RateMax<QM, IPT> &rm)
 {
     if constexpr (!folds<CH>()) {
-        stream_range<K, CH, IPT, DIAG>(jrec, jb, je, ii, xi, eps2, acc, accf);
+        stream_range<K, CH, IPT, DIAG, QM>(jrec, jb, je, ii, xi, eps2, acc, accf, rm);
     } else {
         for (int64_t s0 = jb; s0 < je; s0 += kFold) {
             const int64_t s1 = min(je, s0 + (int64_t)kFold);
-            stream_range<K, CH, IPT, DIAG>(jrec, s0, s1, ii, xi, eps2, acc, accf);
+            stream_range<K, CH, IPT, DIAG, QM>(jrec, s0, s1, ii, xi, eps2, acc, accf, rm);
             fold_partials<K, CH, IPT>(acc, accf);
         }
     }
@@ -412,10 +466,12 @@ __device__ __forceinline__ void stream_folded(const double *__restrict__ jrec, i
 // W waves per workgroup.  SHARE: they share 64*IPT i-particles and each
 // streams its own contiguous part of the workgroup's j-range (sums added
 // through LDS); otherwise they stream the same records for different i.
-template <int K, Chain CH, int IPT, int W, bool SHARE>
+template <int K, Chain CH, int IPT, int W, bool SHARE, bool QM>
 __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, const double *__restrict__ jrec,
                                                                  Path<K> path, double eps2, int64_t j_chunk,
-                                                                 double *__restrict__ out)
+                                                                 double *__restrict__ out,
+                                                                 const double *__restrict__ mass, double G,
+                                                                 double *__restrict__ qpart)
 {
     __shared__ double red[SHARE ? (W - 1) * IPT * (K + 1) * 3 * kWave : 1];
     const int tid = threadIdx.x;
@@ -438,10 +494,15 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
     double xi[IPT][K + 1][3];
     double acc[IPT][K + 1][3];
     float accf[IPT][K + 1][3];
+    RateMax<QM, IPT> rm;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
         const bool ok = ii[q] < n;
+        if constexpr (QM) {
+            rm.gm[q] = ok ? G * mass[ii[q]] : 0.0;
+            rm.q[q] = 0.0;
+        }
 #pragma unroll
         for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -454,10 +515,11 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
     // [jbeg, d0) and [d1, jend) cannot contain one of this workgroup's i.
     const int64_t d0 = max(jbeg, min(jend, ib0));
     const int64_t d1 = max(d0, min(jend, ib1));
-    stream_folded<K, CH, IPT, false>(jrec, jbeg, d0, ii, xi, eps2, acc, accf);
-    stream_folded<K, CH, IPT, true>(jrec, d0, d1, ii, xi, eps2, acc, accf);
-    stream_folded<K, CH, IPT, false>(jrec, d1, jend, ii, xi, eps2, acc, accf);
+    stream_folded<K, CH, IPT, false, QM>(jrec, jbeg, d0, ii, xi, eps2, acc, accf, rm);
+    stream_folded<K, CH, IPT, true, QM>(jrec, d0, d1, ii, xi, eps2, acc, accf, rm);
+    stream_folded<K, CH, IPT, false, QM>(jrec, d1, jend, ii, xi, eps2, acc, accf, rm);
 
+    store_rate<QM, IPT, W>(rm, ii, n, qpart);
     if constexpr (SHARE) {
         reduce_waves<K, IPT, W>(red, wave, lane, acc);
         if (wave != 0) return;
@@ -483,21 +545,41 @@ __global__ void reduce_splits_kernel(int64_t count, int nsplit, const double *__
     out[e] = s;
 }
 
-template <int K, Chain CH, int IPT, int W, bool SHARE>
+// Workgroups of a launch (each writes one rate maximum when QM).
+template <int IPT, int W, bool SHARE>
+int64_t grid_blocks(int64_t n, int nsplit)
+{
+    const int64_t ib = iblock_size(W, SHARE, IPT);
+    return (n + ib - 1) / ib * nsplit;
+}
+
+template <int IPT, int W, bool SHARE, bool QM>
+bool rate_fits(const ForceArgs &a, int nsplit)
+{
+    if constexpr (!QM) return true;
+    const int64_t nb = grid_blocks<IPT, W, SHARE>(a.n, nsplit);
+    if (nb > a.qpart_cap) return false;
+    if (a.q_count) *a.q_count = (int)nb;
+    return true;
+}
+
+template <int K, Chain CH, int IPT, int W, bool SHARE, bool QM>
 hipError_t launch_lds(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
 {
+    if (!rate_fits<IPT, W, SHARE, QM>(a, nsplit)) return hipErrorInvalidValue;
     Path<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     const int64_t ib = iblock_size(W, SHARE, IPT);
     dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
-    hipLaunchKernelGGL((force_kernel<K, CH, IPT, W, SHARE>), grid, dim3(kWave * W), 0, st, a.n, a.mass, path, a.G,
-                       a.eps2, j_chunk, a.k_first, dst);
+    hipLaunchKernelGGL((force_kernel<K, CH, IPT, W, SHARE, QM>), grid, dim3(kWave * W), 0, st, a.n, a.mass, path,
+                       a.G, a.eps2, j_chunk, a.k_first, dst, a.qpart);
     return hipGetLastError();
 }
 
-template <int K, Chain CH, int IPT, int W, bool SHARE>
+template <int K, Chain CH, int IPT, int W, bool SHARE, bool QM>
 hipError_t launch_stream(const ForceArgs &a, int nsplit, int64_t j_chunk, double *dst, hipStream_t st)
 {
+    if (!rate_fits<IPT, W, SHARE, QM>(a, nsplit)) return hipErrorInvalidValue;
     Path<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     hipLaunchKernelGGL((pack_j_kernel<K>), dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a.n,
@@ -506,15 +588,15 @@ hipError_t launch_stream(const ForceArgs &a, int nsplit, int64_t j_chunk, double
     if (e != hipSuccess) return e;
     const int64_t ib = iblock_size(W, SHARE, IPT);
     dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
-    hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT, W, SHARE>), grid, dim3(kWave * W), 0, st, a.n,
-                       (const double *)a.jrec, path, a.eps2, j_chunk, dst);
+    hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT, W, SHARE, QM>), grid, dim3(kWave * W), 0, st, a.n,
+                       (const double *)a.jrec, path, a.eps2, j_chunk, dst, a.mass, a.G, a.qpart);
     return hipGetLastError();
 }
 
 // Shapes: LDS source: 4 waves sharing an i-block; scalar source: 4 waves with
 // their own i (sharing the streamed records) or 16 waves sharing an i-block
 // (one i-particle per lane).
-template <int K, Chain CH>
+template <int K, Chain CH, bool QM>
 hipError_t dispatch_k(const ForceArgs &a, const LaunchShape &sh, int nsplit, int64_t j_chunk, double *dst,
                       hipStream_t st)
 {
@@ -523,42 +605,42 @@ hipError_t dispatch_k(const ForceArgs &a, const LaunchShape &sh, int nsplit, int
         // 1024-thread workgroups: 128 VGPRs per lane, which the LDS-tiled
         // kernel (its j-rows live in VGPRs) cannot meet without spilling.
         if (sh.ipt != 1 || !scalar) return hipErrorInvalidValue;
-        return launch_stream<K, CH, 1, 16, true>(a, nsplit, j_chunk, dst, st);
+        return launch_stream<K, CH, 1, 16, true, QM>(a, nsplit, j_chunk, dst, st);
     }
     if (sh.waves != 4) return hipErrorInvalidValue;
     if (sh.ipt == 1)
-        return scalar ? launch_stream<K, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st)
-                      : launch_lds<K, CH, 1, 4, true>(a, nsplit, j_chunk, dst, st);
+        return scalar ? launch_stream<K, CH, 1, 4, false, QM>(a, nsplit, j_chunk, dst, st)
+                      : launch_lds<K, CH, 1, 4, true, QM>(a, nsplit, j_chunk, dst, st);
     if (sh.ipt == 2)
-        return scalar ? launch_stream<K, CH, 2, 4, false>(a, nsplit, j_chunk, dst, st)
-                      : launch_lds<K, CH, 2, 4, true>(a, nsplit, j_chunk, dst, st);
+        return scalar ? launch_stream<K, CH, 2, 4, false, QM>(a, nsplit, j_chunk, dst, st)
+                      : launch_lds<K, CH, 2, 4, true, QM>(a, nsplit, j_chunk, dst, st);
     return hipErrorInvalidValue;
 }
 
-template <Chain CH>
+template <Chain CH, bool QM>
 hipError_t dispatch(const ForceArgs &a, const LaunchShape &sh, int nsplit, int64_t j_chunk, double *dst,
                     hipStream_t st)
 {
     if constexpr (CH == Chain::Generic) {
         switch (a.K) {
-            case 1: return launch_lds<1, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
-            case 3: return launch_lds<3, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
-            case 5: return launch_lds<5, CH, 1, 4, false>(a, nsplit, j_chunk, dst, st);
+            case 1: return launch_lds<1, CH, 1, 4, false, false>(a, nsplit, j_chunk, dst, st);
+            case 3: return launch_lds<3, CH, 1, 4, false, false>(a, nsplit, j_chunk, dst, st);
+            case 5: return launch_lds<5, CH, 1, 4, false, false>(a, nsplit, j_chunk, dst, st);
             default: return hipErrorInvalidValue;
         }
     } else if constexpr (CH == Chain::Split) {
         // 4th order has no FP32 part: the split chain is the FP64 one
         switch (a.K) {
-            case 1: return dispatch_k<1, Chain::Fp64>(a, sh, nsplit, j_chunk, dst, st);
-            case 2: return dispatch_k<2, CH>(a, sh, nsplit, j_chunk, dst, st);
-            case 3: return dispatch_k<3, CH>(a, sh, nsplit, j_chunk, dst, st);
+            case 1: return dispatch_k<1, Chain::Fp64, QM>(a, sh, nsplit, j_chunk, dst, st);
+            case 2: return dispatch_k<2, CH, QM>(a, sh, nsplit, j_chunk, dst, st);
+            case 3: return dispatch_k<3, CH, QM>(a, sh, nsplit, j_chunk, dst, st);
             default: return hipErrorInvalidValue;
         }
     } else {
         switch (a.K) {
-            case 1: return dispatch_k<1, CH>(a, sh, nsplit, j_chunk, dst, st);
-            case 2: return dispatch_k<2, CH>(a, sh, nsplit, j_chunk, dst, st);
-            case 3: return dispatch_k<3, CH>(a, sh, nsplit, j_chunk, dst, st);
+            case 1: return dispatch_k<1, CH, QM>(a, sh, nsplit, j_chunk, dst, st);
+            case 2: return dispatch_k<2, CH, QM>(a, sh, nsplit, j_chunk, dst, st);
+            case 3: return dispatch_k<3, CH, QM>(a, sh, nsplit, j_chunk, dst, st);
             default: return hipErrorInvalidValue;
         }
     }
@@ -608,11 +690,20 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, 
     nsplit = (int)((a.n + j_chunk - 1) / j_chunk);
     double *dst = nsplit > 1 ? a.partial : a.out;
     hipError_t e;
+    // the fused pair-rate maximum: FP64 and split chains only
+    const bool qm = a.qpart != nullptr;
+    if (qm && chain != Chain::Fp64 && chain != Chain::Split) return hipErrorInvalidValue;
     switch (chain) {
-        case Chain::Fp64: e = dispatch<Chain::Fp64>(a, sh, nsplit, j_chunk, dst, st); break;
-        case Chain::Mixed: e = dispatch<Chain::Mixed>(a, sh, nsplit, j_chunk, dst, st); break;
-        case Chain::Split: e = dispatch<Chain::Split>(a, sh, nsplit, j_chunk, dst, st); break;
-        default: e = dispatch<Chain::Generic>(a, sh, nsplit, j_chunk, dst, st); break;
+        case Chain::Fp64:
+            e = qm ? dispatch<Chain::Fp64, true>(a, sh, nsplit, j_chunk, dst, st)
+                   : dispatch<Chain::Fp64, false>(a, sh, nsplit, j_chunk, dst, st);
+            break;
+        case Chain::Mixed: e = dispatch<Chain::Mixed, false>(a, sh, nsplit, j_chunk, dst, st); break;
+        case Chain::Split:
+            e = qm ? dispatch<Chain::Split, true>(a, sh, nsplit, j_chunk, dst, st)
+                   : dispatch<Chain::Split, false>(a, sh, nsplit, j_chunk, dst, st);
+            break;
+        default: e = dispatch<Chain::Generic, false>(a, sh, nsplit, j_chunk, dst, st); break;
     }
     if (e != hipSuccess || nsplit == 1) return e;
     const int64_t blocks = (per_split + 255) / 256;

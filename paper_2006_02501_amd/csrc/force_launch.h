@@ -28,6 +28,12 @@ struct ForceArgs {
     double *partial;              // split partial sums [nsplit][K+1-k_first][3][n]
     int64_t partial_cap;          // capacity of partial, in doubles
     double *jrec;                 // packed j-records [n][16] (scalar source)
+    // Optional (FP64 and split chains): every workgroup also writes the
+    // largest pair rate G (m_i + m_j) (r^2 + eps^2)^(-3/2) of its pairs to
+    // qpart[block], and *q_count receives the number of workgroups.
+    double *qpart = nullptr;
+    int64_t qpart_cap = 0;
+    int *q_count = nullptr;
 };
 
 // Launch shape of the FP64 / mixed evaluation (the generic initialisation

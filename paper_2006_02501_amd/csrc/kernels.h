@@ -28,6 +28,11 @@ int qmax_partials(int64_t n, int *nsplit, int64_t *j_chunk);
 hipError_t launch_timestep(int64_t n, const double *mass, const double *x, double G, double eps2, double eta,
                            double dir, int mode, double *qpart, int64_t qpart_cap, double *vs, hipStream_t st);
 
+// The same from count maxima already in qpart (an evaluation with the fused
+// pair rate wrote them).
+hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, double *vs,
+                                hipStream_t st);
+
 hipError_t launch_potential(int64_t n, const double *mass, const double *pos, double G, double eps2,
                             double *phi, hipStream_t st);
 

@@ -158,7 +158,8 @@ int64_t partial_capacity(int64_t n_max, int p)
 }
 
 hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
-                         const double *const *path, double *out, int ipt, int nsplit, int jsource, int waves)
+                         const double *const *path, double *out, int ipt, int nsplit, int jsource, int waves,
+                         int *q_count = nullptr)
 {
     ForceArgs a{};
     a.n = s->n;
@@ -172,6 +173,11 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
     a.partial = ctx->partial;
     a.partial_cap = ctx->partial_cap;
     a.jrec = ctx->jrec;
+    if (q_count) {
+        a.qpart = ctx->qpart;
+        a.qpart_cap = ctx->qpart_cap;
+        a.q_count = q_count;
+    }
     hermite::LaunchShape sh{ipt, waves, jsource == 1 ? hermite::JSource::Scalar : hermite::JSource::Lds};
     if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
     HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
@@ -192,8 +198,10 @@ hermite_status check_finite(hermite_ctx *ctx, const double *const *arrays, const
 
 hermite_status alloc_timestep(hermite_ctx *ctx)
 {
-    // the rate pass writes at most ceil(n/256) + 2048 workgroup maxima
-    ctx->qpart_cap = (ctx->n_max + 255) / 256 + 2049;
+    // the rate pass writes at most ceil(n/256) + 2048 workgroup maxima; an
+    // evaluation with the fused rate at most one per workgroup, i.e. at most
+    // (ceil(n/64)) * 64 splits
+    ctx->qpart_cap = std::max<int64_t>((ctx->n_max + 255) / 256 + 2049, (ctx->n_max + 63) / 64 * 64);
     if (hipMalloc((void **)&ctx->qpart, ctx->qpart_cap * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
     if (hipMalloc((void **)&ctx->vs, 4 * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
     if (hipHostMalloc((void **)&ctx->host_vs, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
@@ -221,6 +229,25 @@ void free_ctx(hermite_ctx *ctx)
     if (ctx->vs) (void)hipFree(ctx->vs);
     if (ctx->host_vs) (void)hipHostFree(ctx->host_vs);
     delete ctx;
+}
+
+Chain eval_chain(const hermite_ctx *ctx)
+{
+    return ctx->prm.precision == HERMITE_MIXED ? Chain::Mixed
+           : ctx->prm.precision == HERMITE_SPLIT ? Chain::Split
+                                                 : Chain::Fp64;
+}
+
+// One evaluation of the current path; with q_count, the pair rate is taken
+// along (FP64 and split chains) and the workgroup maxima land in ctx->qpart.
+hermite_status eval_path(hermite_ctx *ctx, hermite_state *s, int *q_count)
+{
+    const int p = ctx->p;
+    const int64_t n3 = 3 * s->n;
+    const double *path[hermite::kMaxPath] = {};
+    for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
+    return run_force(ctx, s, eval_chain(ctx), p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves,
+                     q_count);
 }
 
 }  // namespace
@@ -351,14 +378,7 @@ hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
     if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
     hermite_status st = check_state(ctx, s, false, true);
     if (st != HERMITE_OK) return st;
-    const int p = ctx->p;
-    const int64_t n3 = 3 * s->n;
-    const double *path[hermite::kMaxPath] = {};
-    for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
-    const Chain ch = ctx->prm.precision == HERMITE_MIXED   ? Chain::Mixed
-                     : ctx->prm.precision == HERMITE_SPLIT ? Chain::Split
-                                                           : Chain::Fp64;
-    return run_force(ctx, s, ch, p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves);
+    return eval_path(ctx, s, nullptr);
 }
 
 hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter)
@@ -437,13 +457,24 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
             "step criterion launch");
     HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, dtp, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
             "predict launch");
+    // FP64 and split evaluations take the pair rate along; the mixed one has
+    // only an FP32 1/r, so its criterion is a separate FP64 pass
+    const bool fused = ctx->prm.precision != HERMITE_MIXED;
     for (int it = 0; it < n_iter; ++it) {
-        st = hermite_force_derivs(ctx, s);
-        if (st != HERMITE_OK) return st;
-        // H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
-        HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pred, ctx->prm.G, ctx->prm.eps2, eta, direction, 1,
-                                              ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
-                "step criterion launch");
+        // evaluation, H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
+        if (fused) {
+            int nq = 0;
+            st = eval_path(ctx, s, &nq);
+            if (st != HERMITE_OK) return st;
+            HIP_TRY(ctx, hermite::launch_timestep_fold(ctx->qpart, nq, eta, direction, 1, ctx->vs, ctx->stream),
+                    "step criterion launch");
+        } else {
+            st = eval_path(ctx, s, nullptr);
+            if (st != HERMITE_OK) return st;
+            HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pred, ctx->prm.G, ctx->prm.eps2, eta, direction,
+                                                  1, ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
+                    "step criterion launch");
+        }
         HIP_TRY(ctx, hermite::launch_correct(p, ctx->prm.corrector, it == n_iter - 1 ? 1 : 0, s->n, 0.0, dtp, s->pos,
                                              s->vel, s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
                 "correct launch");

@@ -140,4 +140,12 @@ hipError_t launch_timestep(int64_t n, const double *mass, const double *x, doubl
     return hipGetLastError();
 }
 
+hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, double *vs,
+                                hipStream_t st)
+{
+    if (count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(timestep_kernel, dim3(1), dim3(kQBlock), 0, st, qpart, count, eta, dir, mode, vs);
+    return hipGetLastError();
+}
+
 }  // namespace hermite

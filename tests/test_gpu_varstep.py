@@ -143,6 +143,30 @@ def test_symmetric_step_reversible_on_gpu():
     assert abs(d1["t"]) < 1e-15
 
 
+@pytest.mark.parametrize("launch", [(1, 1, 0, 4), (2, 3, 0, 4), (1, 64, 1, 4), (2, 0, 1, 4), (1, 5, 1, 16)])
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_fused_rate_in_every_launch_shape(launch, precision):
+    # FP64 and split evaluations take the pair rate along (one maximum per
+    # workgroup); the step length must not depend on the launch shape
+    _say("fused rate launch=%s %s" % (launch, precision))
+    w = disc100()
+    eps2 = w["eps2"]
+    o = ho.State(w["mass"], w["x"], w["v"], 3)
+    ho.init_derivs(o, eps2=eps2)
+    h = Hermite(8, len(w["mass"]), precision=precision, eps2=eps2, device=DEV)
+    h.set_launch(*launch)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    for _ in range(3):
+        do = ho.step_symmetric(o, 0.08, 3, eps2=eps2)
+        dg = h.step_symmetric(st, 0.08, 3)
+        assert abs(dg / do - 1.0) <= (1e-13 if precision == "fp64" else 1e-9), (dg, do)
+    g = st.host()
+    h.close()
+    if precision == "fp64":
+        assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+
+
 def test_mixed_symmetric_step_within_force_bound():
     # The mixed evaluation's relative force error delta (<= 1e-6, the bar of
     # the mixed evaluation on a) moves each iterate's x by <= delta a dt^2 / 2
