@@ -282,7 +282,8 @@ hermite_status hermite_ensemble_run(hermite_ctx *ctx, hermite_state *s, const he
 
 /*
  * Launch-shape tuning for hermite_force_derivs.
- *   i_per_thread   1 or 2 i-particles per lane
+ *   i_per_thread   1 or 2 i-particles per lane (3 or 4 with the scalar
+ *                  source and 4-wave workgroups)
  *   j_split        number of j-ranges summed by separate workgroups (0 = auto,
  *                  1..64; an upper bound: it is reduced to one range per 256 j
  *                  and to what the workspace holds, which is 64 ranges while

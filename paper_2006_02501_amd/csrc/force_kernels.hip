@@ -614,6 +614,11 @@ hipError_t dispatch_k(const ForceArgs &a, const LaunchShape &sh, int nsplit, int
     if (sh.ipt == 2)
         return scalar ? launch_stream<K, CH, 2, 4, false, QM>(a, nsplit, j_chunk, dst, st)
                       : launch_lds<K, CH, 2, 4, true, QM>(a, nsplit, j_chunk, dst, st);
+    // 3 or 4 i-particles per lane: scalar source only (the LDS kernel's
+    // j-rows would not fit beside them in VGPRs)
+    if (!scalar) return hipErrorInvalidValue;
+    if (sh.ipt == 3) return launch_stream<K, CH, 3, 4, false, QM>(a, nsplit, j_chunk, dst, st);
+    if (sh.ipt == 4) return launch_stream<K, CH, 4, 4, false, QM>(a, nsplit, j_chunk, dst, st);
     return hipErrorInvalidValue;
 }
 

@@ -310,8 +310,11 @@ hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_
                                   int32_t wg_waves)
 {
     if (!ctx) return HERMITE_E_ARG;
-    if (i_per_thread != 1 && i_per_thread != 2)
-        return fail(ctx, HERMITE_E_ARG, "hermite: i_per_thread must be 1 or 2");
+    if (i_per_thread < 1 || i_per_thread > 4)
+        return fail(ctx, HERMITE_E_ARG, "hermite: i_per_thread must be 1, 2, 3 or 4");
+    if (i_per_thread > 2 && (j_source != 1 || wg_waves != 4))
+        return fail(ctx, HERMITE_E_ARG,
+                    "hermite: 3 or 4 i-particles per lane need the scalar j-source and 4-wave workgroups");
     if (j_split < 0 || j_split > 64) return fail(ctx, HERMITE_E_ARG, "hermite: j_split must be in 0..64");
     if (j_source != 0 && j_source != 1) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0 or 1");
     if (wg_waves != 4 && wg_waves != 16) return fail(ctx, HERMITE_E_ARG, "hermite: wg_waves must be 4 or 16");
@@ -522,7 +525,7 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
         int split;
         float ms;
     };
-    const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {1, 16, 1}};
+    const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {1, 16, 1}};
     int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
     if (s->n > 0) {
         hipEvent_t e0, e1;

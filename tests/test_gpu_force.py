@@ -66,14 +66,15 @@ def test_force_derivs_random_softened(order, precision):
 
 @pytest.mark.parametrize("source", [0, 1])
 @pytest.mark.parametrize("shape", [(1, 1, 4), (1, 3, 4), (2, 1, 4), (2, 5, 4), (2, 0, 4), (1, 64, 4),
-                                   (1, 1, 16), (1, 3, 16), (1, 0, 16)])
+                                   (1, 1, 16), (1, 3, 16), (1, 0, 16), (3, 3, 4), (3, 0, 4), (4, 1, 4),
+                                   (4, 7, 4)])
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_force_derivs_launch_shapes(order, shape, source):
     # (i_per_thread, j_split, wg_waves) x j_source on a ragged N that spans
     # several tiles, splits and workgroups
     _say("force_derivs launch shape", order, shape, source)
-    if shape[2] == 16 and source == 0:
-        pytest.skip("16-wave workgroups use the scalar j-source only")
+    if (shape[2] == 16 or shape[0] > 2) and source == 0:
+        pytest.skip("16-wave workgroups and 3-4 i per lane use the scalar j-source only")
     p = order // 2 - 1
     w, path = disc_path(1500, p)
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
@@ -87,7 +88,8 @@ def test_force_derivs_launch_shapes(order, shape, source):
 def test_set_launch_validation():
     h = Hermite(8, 16, device=DEV)
     from paper_2006_02501_amd import HermiteError
-    for bad in [(3, 0, 1, 4), (1, 65, 1, 4), (1, 0, 2, 4), (1, 0, 1, 8), (2, 0, 1, 16), (1, 0, 0, 16)]:
+    for bad in [(5, 0, 1, 4), (0, 0, 1, 4), (3, 0, 0, 4), (4, 0, 1, 16), (1, 65, 1, 4), (1, 0, 2, 4),
+                (1, 0, 1, 8), (2, 0, 1, 16), (1, 0, 0, 16)]:
         with pytest.raises(HermiteError):
             h.set_launch(*bad)
     h.set_launch(1, 0, 1, 16)
