@@ -188,6 +188,16 @@ def test_step_errors_and_nonfinite():
     h.close()
 
 
+def test_create_reports_allocation_failure():
+    # a workspace far beyond the device's memory: E_ALLOC, nothing left behind
+    _say("create E_ALLOC")
+    with pytest.raises(HermiteError) as ei:
+        Hermite(8, 1 << 40, device=DEV)
+    assert ei.value.status == -3
+    h = Hermite(8, 16, device=DEV)         # the device still works
+    h.close()
+
+
 def test_checkpoint_resume_bitwise_gpu():
     _say("checkpoint resume gpu")
     w, _ = disc_path(500, 1)
