@@ -80,8 +80,14 @@ hermite_status fail(hermite_ctx *ctx, hermite_status st, const std::string &msg)
     return st;
 }
 
+// A failed HIP call also leaves its code in the runtime's per-thread
+// last-error slot, where the caller's next error check (torch's, say) would
+// find it; the library reports through its own status instead, so it clears it.
+void clear_hip_error() { (void)hipGetLastError(); }
+
 hermite_status hip_fail(hermite_ctx *ctx, hipError_t e, const char *where)
 {
+    clear_hip_error();
     std::string m = std::string("hermite: HIP error in ") + where + ": " + hipGetErrorString(e);
     return fail(ctx, HERMITE_E_HIP, m);
 }
@@ -231,6 +237,13 @@ void free_ctx(hermite_ctx *ctx)
     delete ctx;
 }
 
+hermite_status alloc_failed(hermite_ctx *ctx)
+{
+    clear_hip_error();
+    free_ctx(ctx);
+    return HERMITE_E_ALLOC;
+}
+
 Chain eval_chain(const hermite_ctx *ctx)
 {
     return ctx->prm.precision == HERMITE_MIXED ? Chain::Mixed
@@ -273,21 +286,17 @@ hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hi
     ctx->stream = (hipStream_t)hip_stream;
     ctx->partial_cap = partial_capacity(n_max, ctx->p);
     if (ctx->partial_cap > 0 && hipMalloc((void **)&ctx->partial, ctx->partial_cap * sizeof(double)) != hipSuccess) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     if (hipMalloc((void **)&ctx->flag, sizeof(int)) != hipSuccess) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     if (n_max > 0 &&
         hipMalloc((void **)&ctx->jrec, (size_t)n_max * hermite::kJRecDoubles * sizeof(double)) != hipSuccess) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     if (alloc_timestep(ctx) != HERMITE_OK) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     *out = ctx;
     return HERMITE_OK;
@@ -660,10 +669,10 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
               alloc_copy((void **)&ctx->d_iters, nullptr, (size_t)n_sys * sizeof(int32_t)) &&
               alloc_copy((void **)&ctx->flag, nullptr, sizeof(int));
     if (!ok) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        clear_hip_error();
         free_ctx(ctx);
         return HERMITE_E_HIP;
     }
@@ -788,8 +797,7 @@ hermite_status hermite_ensemble_create(const hermite_params *prm, int32_t n_sys,
         ok = hipMemcpy(ctx->d_offsets, offsets, (size_t)(n_sys + 1) * sizeof(int64_t), hipMemcpyHostToDevice) ==
              hipSuccess;
     if (!ok) {
-        free_ctx(ctx);
-        return HERMITE_E_ALLOC;
+        return alloc_failed(ctx);
     }
     *out = ctx;
     return HERMITE_OK;

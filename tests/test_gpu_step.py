@@ -194,7 +194,12 @@ def test_create_reports_allocation_failure():
     with pytest.raises(HermiteError) as ei:
         Hermite(8, 1 << 40, device=DEV)
     assert ei.value.status == -3
-    h = Hermite(8, 16, device=DEV)         # the device still works
+    # the failure is reported through the status only: the caller's next HIP
+    # call (a torch allocation) does not inherit it
+    z = torch.zeros(16, dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    assert float(z.sum()) == 0.0
+    h = Hermite(8, 16, device=DEV)
     h.close()
 
 
