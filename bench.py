@@ -405,6 +405,65 @@ def table1(chunk=200000, etas=(0.08, 0.04, 0.02, 0.01, 0.005), iters=(3, 4), t_e
     return out
 
 
+def other_configs():
+    """The cluster (131,073 bodies, 6th order, eps = 1e-4, dt = 1/4096, P(EC)^2,
+    10 steps; autotuned) and the large disc (1,048,576 bodies, 8th order: one
+    evaluation and one P(EC)^3 step; in the 16k disc's tuned shapes, since
+    timing every candidate at this size would take minutes), in FP64 and
+    mixed precision."""
+    import torch
+    from paper_2006_02501_amd import Hermite
+    from workloads import large_disc, plummer_cluster
+
+    out = {}
+    fixed = {"fp64": (2, 0, 0, 4), "mixed": (1, 0, 1, 4)}
+    for name, w, steps, eval_reps in (("plummer_cluster", plummer_cluster(), 10, 3), ("large_disc", large_disc(), 1, 1)):
+        n = len(w["mass"])
+        order, n_iter, dt = w["order"], w["n_iter"], w["dt"]
+        res = {"n_bodies": n, "order": order, "n_iter": n_iter, "dt": dt, "steps": steps}
+        for prec in ("fp64", "mixed"):
+            h = Hermite(order, n, precision=prec, G=w["G"], eps2=w["eps2"], device="cuda:0")
+            st = h.state(w["mass"], w["x"], w["v"])
+            log("    %s %s: init ..." % (name, prec))
+            t0 = time.perf_counter()
+            h.init(st)
+            torch.cuda.synchronize()
+            t_init = time.perf_counter() - t0
+            h.predict(st, dt)
+            if name == "plummer_cluster":
+                log("    %s %s: autotune ..." % (name, prec))
+                shape = h.autotune(st)
+            else:
+                shape = fixed[prec]
+                h.set_launch(*shape)
+            log("    %s %s: timing ..." % (name, prec))
+            E0 = _energy(h, st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(eval_reps):
+                h.force_derivs(st)
+            torch.cuda.synchronize()
+            t_eval = (time.perf_counter() - t0) / eval_reps
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                h.step(st, dt, n_iter)
+            torch.cuda.synchronize()
+            t_steps = time.perf_counter() - t0
+            E1 = _energy(h, st)
+            h.close()
+            inter = n * (n - 1)
+            res[prec] = {"launch": list(shape), "init_s": t_init, "eval_ms": t_eval * 1e3,
+                         "eval_interactions_per_s": inter / t_eval,
+                         "eval_tflops": FLOPS_PER_INTERACTION[order] * inter / t_eval / 1e12,
+                         "ms_per_step": t_steps / steps * 1e3,
+                         "step_interactions_per_s": steps * n_iter * inter / t_steps,
+                         "energy_rel_change": (E1 - E0) / abs(E0)}
+            log("    %s %s: eval %.2f ms (%.3e interactions/s), step %.2f ms" % (name, prec, t_eval * 1e3,
+                                                                               inter / t_eval, t_steps / steps * 1e3))
+        out[name] = res
+    return out
+
+
 def calibrate_copy(mib=256, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -433,6 +492,8 @@ def main():
     ap.add_argument("--table1", action="store_true",
                     help="also run the Sec. 3.3 N-body test grid (Table 1) to t = 100 pi (a few minutes)")
     ap.add_argument("--table1-only", action="store_true", help="run only the Table 1 grid")
+    ap.add_argument("--other-configs", action="store_true",
+                    help="also time the 131k cluster and the 1M-body disc (about a minute)")
     ap.add_argument("--table1-etas", default="0.08,0.04,0.02,0.01,0.005")
     ap.add_argument("--table1-iters", default="3,4", help="iteration counts of the 8th-order rows")
     ap.add_argument("--eta", type=float, default=0.4,
@@ -527,6 +588,9 @@ def main():
         log("  batched ...")
         out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)
         log("  batched: %s" % json.dumps({k: out["batched"][k] for k in ("fp64", "mixed")}))
+    if args.other_configs:
+        log("  cluster and large disc ...")
+        out["other_configs"] = other_configs()
     if args.table1:
         log("  table 1 ...")
         out["table1"] = table1(etas=tuple(float(e) for e in args.table1_etas.split(",")),
