@@ -59,32 +59,20 @@ __device__ __forceinline__ Slots slots_of(const int64_t *offsets, int sys, int t
     return s;
 }
 
-// Block-wide max (a NaN is dropped) and sum, in a fixed order: xor-shuffle
-// trees inside each wave, then the 8 wave results in wave order.
-__device__ __forceinline__ double block_max(double q, double *buf)
+// Wave-wide max (a NaN is dropped) and sum by xor-shuffle trees (a fixed
+// order); the 8 wave results then meet in LDS, also in a fixed order.
+__device__ __forceinline__ double wave_max(double q)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) q = __builtin_fmax(q, __shfl_xor(q, off, 64));
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = q;
-    __syncthreads();
-    double r = buf[0];
-#pragma unroll
-    for (int w = 1; w < kEnsWaves; ++w) r = __builtin_fmax(r, buf[w]);
-    return r;
+    return q;
 }
 
-__device__ __forceinline__ double block_sum(double v, double *buf)
+__device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = buf[0];
-#pragma unroll
-    for (int w = 1; w < kEnsWaves; ++w) r += buf[w];
-    return r;
+    return v;
 }
 
 // Generic-order initialisation pass K (1, 3, 5) for every system: outputs
@@ -157,6 +145,7 @@ __device__ __forceinline__ void rate_pass(const Slots &s, const double (*sp0)[kE
 {
     q = 0.0;
     pot = 0.0;
+#pragma unroll 4
     for (int j = s.jb; j < s.je; ++j) {
         const double dx = sp0[0][j] - xi[0], dy = sp0[1][j] - xi[1], dz = sp0[2][j] - xi[2];
         const double w = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
@@ -174,9 +163,11 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
     constexpr int K = P;
     __shared__ double sp[K + 1][3][kEnsMaxN];
     __shared__ double sm[kEnsMaxN];
-    __shared__ double red[8][(K + 1) * 3][64];
-    __shared__ double rbuf[kEnsWaves];
+    // j-part sums, [order*3 + component][j-part][i-slot]
+    __shared__ double red[(K + 1) * 3 * kEnsThreads];
+    __shared__ double rq[kEnsWaves], re[kEnsWaves];
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int sys = blockIdx.x;
     const Slots s = slots_of(a.offsets, sys, tid);
     const int64_t n = a.n, n3 = 3 * n;
@@ -196,10 +187,16 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
     const double gmi = a.G * mi;
     if (s.jp == 0) sm[s.islot] = gmi;
 
+    // Barriers.  LDS is written in three places -- the iterate's path (sp),
+    // the j-part sums and wave maxima (red, rq), and the positions for the
+    // criterion pass (sp[0]) -- each right after a barrier that every read of
+    // the previous contents precedes, and read after the one barrier that
+    // follows the writes.  So an iteration takes two barriers and the
+    // end-of-step pass two.
+    //
     // positions of the state into LDS, then the start-of-step criterion (and
-    // the energy for E0 on a system's first call)
+    // the energy, for E0 on a system's first call and for the records)
     auto share_x = [&]() {
-        __syncthreads();
         if (s.jp == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) sp[0][c][s.islot] = x[c];
@@ -209,15 +206,27 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
     auto energy_and_rate = [&](bool want_pot, double &qmax, double &E) {
         double q, pot;
         rate_pass(s, sp[0], sm, x, gmi, a.eps2, want_pot, q, pot);
-        qmax = block_max(q, rbuf);
-        E = 0.0;
+        const double qw = wave_max(q);
+        double ew = 0.0;
         if (want_pot) {
             const double kin = (s.jp == 0 && s.live) ? 0.5 * mi * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) : 0.0;
-            E = block_sum(kin - 0.5 * mi * pot, rbuf);
+            ew = wave_sum(kin - 0.5 * mi * pot);
+        }
+        if (lane == 0) {
+            rq[wave] = qw;
+            re[wave] = ew;
+        }
+        __syncthreads();
+        qmax = rq[0];
+        E = re[0];
+#pragma unroll
+        for (int w = 1; w < kEnsWaves; ++w) {
+            qmax = __builtin_fmax(qmax, rq[w]);
+            E += re[w];
         }
     };
 
-    share_x();
+    share_x();   // (its barrier also publishes sm)
     double qm, E;
     const bool first = st.steps == 0;
     energy_and_rate(first, qm, E);
@@ -249,7 +258,6 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
         }
         double a1[K + 1][3], x1[3], v1[3];
         for (int it = 0; it < cfg.n_iter; ++it) {
-            __syncthreads();
             if (s.jp == 0) {
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
@@ -263,6 +271,9 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
             double q = 0.0;
+            // two pairs in flight where the registers allow it (not at 8th order)
+            constexpr int kUnr = K >= 3 ? 1 : 2;
+#pragma unroll kUnr
             for (int j = s.jb; j < s.je; ++j) {
                 double r[3], vv[3], aa[3], jj[3];
 #pragma unroll
@@ -282,28 +293,27 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
                 chain_accumulate<K, double>(r, vv, aa, jj, m * r3, rinv2, acc);
                 q = __builtin_fmax(q, (gmi + m) * r3);
             }
-            // j-part sums, one 64-slot group at a time, in j-part order
-            for (int grp = 0; grp < s.NI / 64; ++grp) {
-                __syncthreads();
-                if (s.islot / 64 == grp) {
+            // j-part sums added in j-part order; the block's largest pair rate
 #pragma unroll
-                    for (int k = 0; k <= K; ++k)
+            for (int k = 0; k <= K; ++k)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) red[s.jp][k * 3 + c][s.islot % 64] = acc[k][c];
+                for (int c = 0; c < 3; ++c) red[((k * 3 + c) * s.JP + s.jp) * s.NI + s.islot] = acc[k][c];
+            const double qw = wave_max(q);
+            if (lane == 0) rq[wave] = qw;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double *rr = red + (k * 3 + c) * s.JP * s.NI + s.islot;
+                    double tsum = rr[0];
+                    for (int p2 = 1; p2 < s.JP; ++p2) tsum += rr[p2 * s.NI];
+                    a1[k][c] = tsum;
                 }
-                __syncthreads();
-                if (s.islot / 64 == grp) {
+            double qb = rq[0];
 #pragma unroll
-                    for (int k = 0; k <= K; ++k)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            double tsum = red[0][k * 3 + c][s.islot % 64];
-                            for (int p2 = 1; p2 < s.JP; ++p2) tsum += red[p2][k * 3 + c][s.islot % 64];
-                            a1[k][c] = tsum;
-                        }
-                }
-            }
-            const double Hp = cfg.eta / sqrt(block_max(q, rbuf));
+            for (int w = 1; w < kEnsWaves; ++w) qb = __builtin_fmax(qb, rq[w]);
+            const double Hp = cfg.eta / sqrt(qb);
             if (!(Hp > 0.0) || !__builtin_isfinite(Hp)) {
                 failed = true;
                 break;
