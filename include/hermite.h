@@ -85,8 +85,9 @@ typedef struct {
     int32_t compensated;   /* nonzero: x, v and t take each step's increments by
                               compensated (Kahan) summation, the option Sec. 3.2
                               uses for its 8th-order runs; the state then carries
-                              the compensation terms (comp, t_comp).  Not
-                              available in the batched form (E_ARG there).       */
+                              the compensation terms (comp, t_comp).  The
+                              batched form compensates x and v (its t is a step
+                              count); the ensemble form does not offer it (E_ARG). */
     int32_t reserved;      /* set to 0                                              */
 } hermite_params;
 
@@ -207,8 +208,9 @@ hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, doubl
  * Batched form: n_sys independent systems concatenated in one state
  * (particles offsets[s] .. offsets[s+1]-1 belong to system s; offsets is a
  * HOST array of n_sys+1 nondecreasing values starting at 0, each system of
- * 1..64 particles).  Pair sums run only inside a system.  params.compensated
- * must be 0 (E_ARG).  All steps of all
+ * 1..64 particles).  Pair sums run only inside a system.  precision
+ * HERMITE_SPLIT is not offered (E_ARG).  With params.compensated the state's
+ * comp array is required and hermite_batch_init zeroes it.  All steps of all
  * systems run in one persistent kernel launch, replayed from a captured HIP
  * graph; systems are packed into 64-lane wavefronts and handed out longest
  * first from a device work counter.

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                                                            double *__restrict__ deriv,
                                                            const double *__restrict__ dt_sys, int n_steps,
                                                            int n_iter, const int *__restrict__ iters, double G,
-                                                           double eps2)
+                                                           double eps2, double *__restrict__ comp)
 {
     constexpr int K = P;
     __shared__ double sm[kLanes];
@@ -134,6 +134,10 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
         const int my_iter = (iters && active) ? iters[li.sys] : bin_iter;
 
         double x[3], v[3], d[2 * P][3];
+        // Kahan compensation of x and v (with comp, the option of Sec. 3.2):
+        // the carried terms, and the ones the latest correction produced
+        double cx[3] = {0.0, 0.0, 0.0}, cv[3] = {0.0, 0.0, 0.0};
+        double ncx[3] = {0.0, 0.0, 0.0}, ncv[3] = {0.0, 0.0, 0.0};
         double dt = 1.0;
         if (active) {
             dt = dt_sys[li.sys];
@@ -141,6 +145,10 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             for (int c = 0; c < 3; ++c) {
                 x[c] = pos[c * n + li.g];
                 v[c] = vel[c * n + li.g];
+                if (comp) {
+                    cx[c] = comp[c * n + li.g];
+                    cv[c] = comp[n3 + c * n + li.g];
+                }
 #pragma unroll
                 for (int k = 0; k < 2 * P; ++k) d[k][c] = deriv[k * n3 + c * n + li.g];
             }
@@ -246,7 +254,13 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         const double s = (k & 1) ? (a1[k][c] - d[k][c]) : (a1[k][c] + d[k][c]);
                         dv = __builtin_fma(dv, dt, CV[P][k] * s);
                     }
-                    v1[c] = __builtin_fma(dv, dt, v[c]);
+                    if (comp) {
+                        const double y = dv * dt - cv[c];
+                        v1[c] = v[c] + y;
+                        ncv[c] = (v1[c] - v[c]) - y;
+                    } else {
+                        v1[c] = __builtin_fma(dv, dt, v[c]);
+                    }
                     double dx = 0.0;
 #pragma unroll
                     for (int k = P + 1; k >= 1; --k) {
@@ -254,7 +268,13 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         dx = __builtin_fma(dx, dt, CX[CORR][P][k] * s);
                     }
                     dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1[c] + v[c]));
-                    x1[c] = __builtin_fma(dx, dt, x[c]);
+                    if (comp) {
+                        const double y = dx * dt - cx[c];
+                        x1[c] = x[c] + y;
+                        ncx[c] = (x1[c] - x[c]) - y;
+                    } else {
+                        x1[c] = __builtin_fma(dx, dt, x[c]);
+                    }
                 }
                 if (it + 1 < my_iter) {
 #pragma unroll
@@ -290,6 +310,8 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                 for (int k = 0; k <= P; ++k) d[k][c] = a1[k][c];
                 x[c] = x1[c];
                 v[c] = v1[c];
+                cx[c] = ncx[c];
+                cv[c] = ncv[c];
             }
         }
         if (active) {
@@ -297,6 +319,10 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             for (int c = 0; c < 3; ++c) {
                 pos[c * n + li.g] = x[c];
                 vel[c * n + li.g] = v[c];
+                if (comp) {
+                    comp[c * n + li.g] = cx[c];
+                    comp[n3 + c * n + li.g] = cv[c];
+                }
 #pragma unroll
                 for (int k = 0; k < 2 * P; ++k) deriv[k * n3 + c * n + li.g] = d[k][c];
             }
@@ -307,13 +333,13 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
 template <int P, bool MIXED>
 hipError_t run_pm(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
                   double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
-                  double eps2, int wg, hipStream_t st)
+                  double eps2, double *comp, int wg, hipStream_t st)
 {
     const dim3 g(wg), b(kLanes);
     switch (corrector) {
-        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
-        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
-        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2); break;
+        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
+        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
+        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -354,16 +380,17 @@ hipError_t launch_batch_init(const BatchPlan &pl, int p, int64_t n, const double
 
 hipError_t launch_batch_run(const BatchPlan &pl, int p, bool mixed, int corrector, int64_t n, const double *mass,
                             double *pos, double *vel, double *deriv, const double *dt_sys, int n_steps, int n_iter,
-                            const int *iters, double G, double eps2, int n_workgroups, hipStream_t st)
+                            const int *iters, double G, double eps2, double *comp, int n_workgroups,
+                            hipStream_t st)
 {
     if (pl.n_bins <= 0 || n <= 0 || n_steps <= 0) return hipSuccess;
     if (n_workgroups < 1) n_workgroups = 1;
 #define HERMITE_BATCH_CASE(PP)                                                                                     \
     case PP:                                                                                                       \
         return mixed ? run_pm<PP, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,   \
-                                        G, eps2, n_workgroups, st)                                                 \
+                                        G, eps2, comp, n_workgroups, st)                                                 \
                      : run_pm<PP, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,  \
-                                         G, eps2, n_workgroups, st);
+                                         G, eps2, comp, n_workgroups, st);
     switch (p) {
         HERMITE_BATCH_CASE(1)
         HERMITE_BATCH_CASE(2)

@@ -54,10 +54,11 @@ hipError_t launch_batch_init(const BatchPlan &plan, int p, int64_t n, const doub
 
 // iters: per-system iteration counts (device, [n_sys], each 1..64) or null
 // for n_iter everywhere.
+// comp: [2][3][n] Kahan compensation of x and v, or null.
 hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int corrector, int64_t n,
                             const double *mass, double *pos, double *vel, double *deriv, const double *dt_sys,
-                            int n_steps, int n_iter, const int *iters, double G, double eps2, int n_workgroups,
-                            hipStream_t st);
+                            int n_steps, int n_iter, const int *iters, double G, double eps2, double *comp,
+                            int n_workgroups, hipStream_t st);
 
 hipError_t launch_reset_counter(int *counter, hipStream_t st);
 

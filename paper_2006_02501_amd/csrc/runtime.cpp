@@ -58,13 +58,13 @@ struct hermite_ctx {
     hipGraphExec_t graph_exec = nullptr;
     struct Key {
         const double *mass, *dt;
-        double *pos, *vel, *deriv;
+        double *pos, *vel, *deriv, *comp;
         int n_steps, n_iter, workgroups;
         bool per_system;
         bool operator==(const Key &o) const
         {
             return mass == o.mass && dt == o.dt && pos == o.pos && vel == o.vel && deriv == o.deriv &&
-                   n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups &&
+                   comp == o.comp && n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups &&
                    per_system == o.per_system;
         }
     } key{};
@@ -610,7 +610,6 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
     *out = nullptr;
     hermite_status st = check_params(prm, msg);
     if (st != HERMITE_OK) return st;
-    if (prm->compensated) return HERMITE_E_ARG;   // the batched kernel adds plainly
     if (prm->precision == HERMITE_SPLIT) return HERMITE_E_ARG;
     if (n_sys < 0 || (n_sys > 0 && !offsets)) return HERMITE_E_ARG;
     if (n_sys > 0 && offsets[0] != 0) return HERMITE_E_ARG;
@@ -702,6 +701,8 @@ hermite_status hermite_batch_init(hermite_ctx *ctx, hermite_state *s)
     HIP_TRY(ctx, hermite::launch_batch_init(plan_of(ctx), ctx->p, s->n, s->mass, s->pos, s->vel, s->deriv,
                                             ctx->prm.G, ctx->prm.eps2, ctx->stream),
             "batch init launch");
+    if (ctx->prm.compensated && s->n > 0)
+        HIP_TRY(ctx, hipMemsetAsync(s->comp, 0, (size_t)6 * s->n * sizeof(double), ctx->stream), "comp clear");
     s->initialized = 1;
     return HERMITE_OK;
 }
@@ -734,7 +735,8 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
     int wg = ctx->batch_workgroups;
     if (wg <= 0) wg = std::min<int>(ctx->n_bins, 256 * 8);
     const bool per_system = iters_host != nullptr;
-    hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, n_steps, per_system ? 0 : n_iter, wg, per_system};
+    hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, comp_of(ctx, s), n_steps,
+                         per_system ? 0 : n_iter, wg, per_system};
     if (!ctx->graph_exec || !(key == ctx->key)) {
         if (ctx->graph_exec) { (void)hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
         if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
@@ -744,7 +746,7 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
         hipError_t e2 = hermite::launch_batch_run(plan_of(ctx), ctx->p, ctx->prm.precision == HERMITE_MIXED,
                                                   ctx->prm.corrector, s->n, s->mass, s->pos, s->vel, s->deriv,
                                                   dt_sys, n_steps, n_iter, per_system ? ctx->d_iters : nullptr,
-                                                  ctx->prm.G, ctx->prm.eps2, wg, cs);
+                                                  ctx->prm.G, ctx->prm.eps2, comp_of(ctx, s), wg, cs);
         hipGraph_t g = nullptr;
         hipError_t e3 = hipStreamEndCapture(cs, &g);
         if (e1 != hipSuccess) return hip_fail(ctx, e1, "graph capture (counter reset)");

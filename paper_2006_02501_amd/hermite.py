@@ -128,10 +128,10 @@ class DeviceState:
         if with_pred:
             self.pred = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
             self.eval = torch.zeros((p + 1, 3, n), dtype=torch.float64, device=dev)
-            # compensation terms of x and v (used with compensated summation)
-            self.comp = torch.zeros((2, 3, n), dtype=torch.float64, device=dev)
         else:
-            self.pred = self.eval = self.comp = None
+            self.pred = self.eval = None
+        # compensation terms of x and v (used with compensated summation)
+        self.comp = torch.zeros((2, 3, n), dtype=torch.float64, device=dev)
         self.c = StateC()
         self.c.n = n
         self.c.mass = self.mass.data_ptr()
@@ -140,7 +140,7 @@ class DeviceState:
         self.c.deriv = self.deriv.data_ptr()
         self.c.pred = self.pred.data_ptr() if with_pred else None
         self.c.eval = self.eval.data_ptr() if with_pred else None
-        self.c.comp = self.comp.data_ptr() if with_pred else None
+        self.c.comp = self.comp.data_ptr()
         self.c.t = float(t)
         self.c.t_comp = 0.0
         self.c.initialized = 0
@@ -168,8 +168,8 @@ class DeviceState:
         if self.pred is not None:
             d["pred"] = [q for q in self.pred.cpu().numpy()]
             d["eval"] = [q for q in self.eval.cpu().numpy()]
-            comp = self.comp.cpu().numpy()
-            d["cx"], d["cv"], d["t_comp"] = comp[0], comp[1], self.c.t_comp
+        comp = self.comp.cpu().numpy()
+        d["cx"], d["cv"], d["t_comp"] = comp[0], comp[1], self.c.t_comp
         return d
 
 
@@ -266,7 +266,7 @@ class BatchHermite:
     """Batched form: many independent systems advanced in one persistent launch."""
 
     def __init__(self, order, offsets, precision="fp64", corrector="modified", G=1.0, eps2=0.0,
-                 check_finite=False, device="cuda:0"):
+                 check_finite=False, device="cuda:0", compensated=False):
         self.lib = load_library()
         self.order = order
         self.p = order // 2 - 1
@@ -274,7 +274,7 @@ class BatchHermite:
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.n_sys = self.offsets.shape[0] - 1
         self.prm = Params(order, PRECISIONS[precision], CORRECTORS[corrector], 1 if check_finite else 0,
-                          float(G), float(eps2))
+                          float(G), float(eps2), 1 if compensated else 0, 0)
         self.ctx = ctypes.c_void_p()
         _check(None, self.lib.hermite_batch_create(
             ctypes.byref(self.prm), int(self.n_sys),

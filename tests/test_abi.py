@@ -90,8 +90,8 @@ def test_batch_create_rejects_bad_layout(offsets):
     assert not ctx.value
 
 
-@pytest.mark.parametrize("precision,compensated", [(0, 1), (2, 0)])
-def test_batch_create_rejects_compensated_and_split(precision, compensated):
+@pytest.mark.parametrize("precision,compensated", [(2, 0), (2, 1)])
+def test_batch_create_rejects_split(precision, compensated):
     lib = load_library()
     ctx = ctypes.c_void_p()
     p = Params(8, precision, 0, 0, 1.0, 0.0, compensated, 0)

@@ -160,3 +160,101 @@ def test_compensated_needs_comp_array():
         h.init(st)
     assert ei.value.status == -1
     h.close()
+
+
+# --- batched form -------------------------------------------------------------
+
+def test_batched_compensated_matches_oracle():
+    # three systems (Kepler 4-, 8th-order copies and a 5-body cluster) in one
+    # compensated persistent launch against the oracle's compensated steps
+    _say("batched compensated vs oracle")
+    from paper_2006_02501_amd import BatchHermite
+
+    kep = kepler_two_body(e=0.5)
+    rng = np.random.default_rng(5)
+    cl = dict(mass=np.concatenate([[1.0], rng.uniform(1e-6, 1e-4, 4)]),
+              x=np.concatenate([np.zeros((3, 1)), rng.normal(size=(3, 4))], axis=1), v=np.zeros((3, 5)))
+    r = np.sqrt((cl["x"][:, 1:] ** 2).sum(axis=0))
+    cl["v"][:, 1:] = np.cross(np.array([0.0, 0.0, 1.0]), cl["x"][:, 1:].T).T / r ** 1.5
+    systems = [kep, kep, cl]
+    mass = np.concatenate([w["mass"] for w in systems])
+    x = np.ascontiguousarray(np.concatenate([w["x"] for w in systems], axis=1))
+    v = np.ascontiguousarray(np.concatenate([w["v"] for w in systems], axis=1))
+    off = np.array([0, 2, 4, 9], dtype=np.int64)
+    dts = np.array([kep["period"] / 200, kep["period"] / 150, 0.002])
+    steps = 50
+    bh = BatchHermite(8, off, compensated=True, device=DEV)
+    st = bh.state(mass, x, v)
+    bh.init(st)
+    bh.run(st, dts, steps, 3)
+    g = st.host()
+    bh.close()
+    for k, w in enumerate(systems):
+        o = ho.State(w["mass"], w["x"], w["v"], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, dts[k], 3, compensated=True)
+        sl = slice(off[k], off[k + 1])
+        assert rel_max(g["x"][:, sl], o.x) <= 1e-11 and rel_max(g["v"][:, sl], o.v) <= 1e-11, k
+    assert np.abs(g["cx"]).max() <= 4 * np.spacing(np.abs(g["x"]).max())
+
+
+def test_batched_free_particles_exact():
+    # 64 one-body systems (no force): each x is the rational sum of its
+    # rounded increments; compensated within one ulp, plain far off
+    _say("batched free particles")
+    from paper_2006_02501_amd import BatchHermite
+
+    k = 64
+    rng = np.random.default_rng(9)
+    x0 = rng.uniform(0.5, 2.0, k)
+    v0 = rng.uniform(0.1, 1.0, k) / 3.0
+    dt = 0.1
+    steps = 10000
+    res = {}
+    for comp in (True, False):
+        bh = BatchHermite(4, np.arange(k + 1, dtype=np.int64), compensated=comp, device=DEV)
+        st = bh.state(np.ones(k), np.stack([x0, np.zeros(k), np.zeros(k)]), np.stack([v0, np.zeros(k), np.zeros(k)]))
+        bh.init(st)
+        bh.run(st, np.full(k, dt), steps, 1)
+        res[comp] = st.host()["x"][0]
+        bh.close()
+    errs = {}
+    for comp in (True, False):
+        e = []
+        for i in range(k):
+            exact = Fraction(float(x0[i])) + steps * Fraction(float(np.float64(v0[i]) * dt))
+            e.append(float(abs(Fraction(float(res[comp][i])) - exact) / Fraction(float(np.spacing(res[comp][i])))))
+        errs[comp] = np.array(e)
+    assert errs[True].max() <= 1.0, errs[True].max()
+    assert errs[False].max() > 50.0, errs[False].max()
+
+
+def test_batched_compensation_lowers_round_off():
+    # Sec. 3.2 on the batched form: 16 copies of the e = 0.1 Kepler orbit,
+    # 8th order, dt = 2^-5, 4 orbits, energy after every step
+    _say("batched compensated kepler round-off")
+    from paper_2006_02501_amd import BatchHermite
+
+    w = kepler_two_body(e=0.1)
+    k = 16
+    mass = np.tile(w["mass"], k)
+    x = np.ascontiguousarray(np.tile(w["x"], (1, k)))
+    v = np.ascontiguousarray(np.tile(w["v"], (1, k)))
+    off = np.arange(0, 2 * k + 1, 2, dtype=np.int64)
+    dt = 2.0 ** -5
+    worst = {}
+    for comp in (False, True):
+        bh = BatchHermite(8, off, eps2=1e-16, compensated=comp, device=DEV)
+        st = bh.state(mass, x, v)
+        bh.init(st)
+        E0 = ho.energy(w["mass"], w["x"], w["v"], eps2=1e-16)
+        wst = 0.0
+        for _ in range(int(4 * 2 * np.pi / dt)):
+            bh.run(st, np.full(k, dt), 1, 3)
+            d = st.host()
+            wst = max(wst, abs(ho.energy(d["mass"][:2], d["x"][:, :2], d["v"][:, :2], eps2=1e-16) / E0 - 1.0))
+        bh.close()
+        worst[comp] = wst
+    assert worst[False] < 1e-14
+    assert worst[True] < 0.5 * worst[False], worst
