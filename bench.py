@@ -492,6 +492,7 @@ def main():
     ap.add_argument("--table1", action="store_true",
                     help="also run the Sec. 3.3 N-body test grid (Table 1) to t = 100 pi (a few minutes)")
     ap.add_argument("--table1-only", action="store_true", help="run only the Table 1 grid")
+    ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
     ap.add_argument("--other-configs", action="store_true",
                     help="also time the 131k cluster and the 1M-body disc (about a minute)")
     ap.add_argument("--table1-etas", default="0.08,0.04,0.02,0.01,0.005")
@@ -515,6 +516,9 @@ def main():
         etas = tuple(float(e) for e in args.table1_etas.split(","))
         iters = tuple(int(q) for q in args.table1_iters.split(","))
         print(json.dumps({"table1": table1(etas=etas, iters=iters)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched(args.batched_steps, per_system=not args.no_per_system)}), flush=True)
         return
 
     calib = calibrate_copy() if args.calibrate_copy else None

@@ -103,7 +103,7 @@ __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
 
 __device__ constexpr double kInvB[9] = {0.0, 1.0, 1.0 / 2.0, 1.0 / 3.0, 1.0 / 4.0, 1.0 / 5.0, 1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0};
 
-template <int P, bool MIXED, int CORR>
+template <int P, bool MIXED, int CORR, bool COMP>
 __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t n, const double *__restrict__ mass,
                                                            double *__restrict__ pos, double *__restrict__ vel,
                                                            double *__restrict__ deriv,
@@ -112,6 +112,8 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                                                            double eps2, double *__restrict__ comp)
 {
     constexpr int K = P;
+    // the 8th-order FP64 kernel with compensation would exceed 256 registers
+    constexpr int kPairUnroll = (P == 3 && !MIXED && COMP) ? 1 : 2;
     __shared__ double sm[kLanes];
     __shared__ float smf[kLanes];
     __shared__ double sp[K + 1][3][kLanes];
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
         const int my_iter = (iters && active) ? iters[li.sys] : bin_iter;
 
         double x[3], v[3], d[2 * P][3];
-        // Kahan compensation of x and v (with comp, the option of Sec. 3.2):
+        // Kahan compensation of x and v (COMP, the option of Sec. 3.2):
         // the carried terms, and the ones the latest correction produced
         double cx[3] = {0.0, 0.0, 0.0}, cv[3] = {0.0, 0.0, 0.0};
         double ncx[3] = {0.0, 0.0, 0.0}, ncv[3] = {0.0, 0.0, 0.0};
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             for (int c = 0; c < 3; ++c) {
                 x[c] = pos[c * n + li.g];
                 v[c] = vel[c * n + li.g];
-                if (comp) {
+                if constexpr (COMP) {
                     cx[c] = comp[c * n + li.g];
                     cv[c] = comp[n3 + c * n + li.g];
                 }
@@ -203,6 +205,9 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         acc[k][c] = 0.0;
                         accf[k][c] = 0.0f;
                     }
+                // two pair chains in flight per lane: one wave alone on a SIMD
+                // is latency-bound (same summation order)
+#pragma unroll kPairUnroll
                 for (int t = 0; t < li.maxlen; ++t) {
                     const int j = li.lo + t;
                     const bool act = active && j < li.hi && j != lane;
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         const double s = (k & 1) ? (a1[k][c] - d[k][c]) : (a1[k][c] + d[k][c]);
                         dv = __builtin_fma(dv, dt, CV[P][k] * s);
                     }
-                    if (comp) {
+                    if constexpr (COMP) {
                         const double y = dv * dt - cv[c];
                         v1[c] = v[c] + y;
                         ncv[c] = (v1[c] - v[c]) - y;
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                         dx = __builtin_fma(dx, dt, CX[CORR][P][k] * s);
                     }
                     dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1[c] + v[c]));
-                    if (comp) {
+                    if constexpr (COMP) {
                         const double y = dx * dt - cx[c];
                         x1[c] = x[c] + y;
                         ncx[c] = (x1[c] - x[c]) - y;
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             for (int c = 0; c < 3; ++c) {
                 pos[c * n + li.g] = x[c];
                 vel[c * n + li.g] = v[c];
-                if (comp) {
+                if constexpr (COMP) {
                     comp[c * n + li.g] = cx[c];
                     comp[n3 + c * n + li.g] = cv[c];
                 }
@@ -330,19 +335,32 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
     }
 }
 
+template <int P, bool MIXED, bool COMP>
+hipError_t run_pmc(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
+                   double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
+                   double eps2, double *comp, int wg, hipStream_t st)
+{
+    const dim3 g(wg), b(kLanes);
+    switch (corrector) {
+        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
+        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
+        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Compensation is a template switch so that the plain kernel carries no
+// compensation registers.
 template <int P, bool MIXED>
 hipError_t run_pm(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
                   double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
                   double eps2, double *comp, int wg, hipStream_t st)
 {
-    const dim3 g(wg), b(kLanes);
-    switch (corrector) {
-        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return comp ? run_pmc<P, MIXED, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,
+                                          G, eps2, comp, wg, st)
+                : run_pmc<P, MIXED, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,
+                                           G, eps2, comp, wg, st);
 }
 
 template <int K>

@@ -64,17 +64,18 @@ def test_force_derivs_random_softened(order, precision):
     assert within(err, tol), (err.max(axis=1), tol)
 
 
-@pytest.mark.parametrize("source", [0, 1])
-@pytest.mark.parametrize("shape", [(1, 1, 4), (1, 3, 4), (2, 1, 4), (2, 5, 4), (2, 0, 4), (1, 64, 4),
-                                   (1, 1, 16), (1, 3, 16), (1, 0, 16), (3, 3, 4), (3, 0, 4), (4, 1, 4),
-                                   (4, 7, 4)])
+_SHAPES = [(1, 1, 4), (1, 3, 4), (2, 1, 4), (2, 5, 4), (2, 0, 4), (1, 64, 4), (1, 1, 16), (1, 3, 16),
+           (1, 0, 16), (3, 3, 4), (3, 0, 4), (4, 1, 4), (4, 7, 4)]
+# 16-wave workgroups and 3-4 i per lane exist only with the scalar j-source
+_LAUNCHES = [(sh, src) for sh in _SHAPES for src in (0, 1) if src == 1 or (sh[2] == 4 and sh[0] <= 2)]
+
+
+@pytest.mark.parametrize("shape,source", _LAUNCHES)
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_force_derivs_launch_shapes(order, shape, source):
     # (i_per_thread, j_split, wg_waves) x j_source on a ragged N that spans
     # several tiles, splits and workgroups
     _say("force_derivs launch shape", order, shape, source)
-    if (shape[2] == 16 or shape[0] > 2) and source == 0:
-        pytest.skip("16-wave workgroups and 3-4 i per lane use the scalar j-source only")
     p = order // 2 - 1
     w, path = disc_path(1500, p)
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
