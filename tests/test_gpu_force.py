@@ -120,21 +120,53 @@ def test_force_derivs_bitwise_reproducible():
     assert np.array_equal(c, d)
 
 
-def test_force_derivs_full_size_sampled():
-    # Disc of 16384 bodies (8th order) in the launch configuration the
-    # benchmark times; 512 sampled i-particles checked against the oracle.
-    _say("force_derivs N=16384 sampled")
+# Launch shapes (i_per_thread, j_split, j_source, wg_waves) that the
+# benchmark's autotuner picks on the 16k disc and that its traffic profile
+# was taken with.
+BENCH_SHAPES = {"fp64": (2, 4, 0, 4), "mixed": (1, 64, 1, 4), "split": (1, 64, 1, 4)}
+
+
+def _eval_autotuned(order, mass, path, precision):
+    p = order // 2 - 1
+    n = len(mass)
+    h = Hermite(order, n, precision=precision, device=DEV)
+    st = h.state(mass, path[0], path[1])
+    for k in range(p + 1):
+        st.pred[k].copy_(torch.as_tensor(np.asarray(path[k], dtype=np.float64).reshape(3, n)))
+    shape = h.autotune(st)
+    h.force_derivs(st)
+    out = st.eval.cpu().numpy()
+    h.close()
+    return out, shape
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_derivs_full_size_sampled(precision):
+    # Disc of 16384 bodies (8th order): the default launch, the launch the
+    # benchmark times, and whatever the autotuner picks on this device; 512
+    # sampled i-particles checked against the oracle, and (FP64) the three
+    # runs against each other.
+    _say("force_derivs N=16384 sampled", precision)
     n = 16384
     w, path = disc_path(n, 3)
     rng = np.random.default_rng(99)
     il = np.sort(rng.choice(n, 512, replace=False))
     il[0] = 0                     # the central body
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
-    for precision, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
-        g = _eval_gpu(8, w["mass"], path, precision)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    g_def = _eval_gpu(8, w["mass"], path, precision)
+    g_bench = _eval_gpu(8, w["mass"], path, precision, launch=BENCH_SHAPES[precision])
+    g_tuned, shape = _eval_autotuned(8, w["mass"], path, precision)
+    for name, g in (("default", g_def), ("bench", g_bench), ("autotuned %s" % (shape,), g_tuned)):
         err = deriv_error(g[:, :, il], o, mag, None if precision == "fp64" else nat)
-        _say("  %s max err per order %s" % (precision, err.max(axis=1)))
-        assert within(err, tol), (precision, err.max(axis=1))
+        _say("  %s %s max err per order %s" % (precision, name, err.max(axis=1)))
+        assert within(err, tol), (precision, name, err.max(axis=1))
+    if precision == "fp64":
+        # every launch shape sums the same FP64 terms; they differ only in
+        # the order of the additions
+        scale = np.abs(g_bench).max(axis=(1, 2), keepdims=True)
+        for g in (g_def, g_tuned):
+            assert (np.abs(g - g_bench) / scale).max() <= 1e-13
 
 
 @pytest.mark.parametrize("order", [4, 6, 8])

@@ -81,15 +81,17 @@ def test_split_random_softened(order):
     assert _ok(deriv_error(g, o, mag, nat)[2:], TOL_MIXED[2:p + 1])
 
 
-def test_split_full_size_sampled():
-    # the 16k disc at its full size in the default launch shape, 192 sampled i
-    _say("split full size 16384")
+@pytest.mark.parametrize("launch", [None, (1, 64, 1, 4)])
+def test_split_full_size_sampled(launch):
+    # the 16k disc at its full size, 192 sampled i, in the default launch shape
+    # and in the one the benchmark times
+    _say("split full size 16384", launch)
     w, path = disc_path(16384, 3)
     rng = np.random.default_rng(16)
     il = np.sort(rng.choice(16384, 192, replace=False))
     il[0], il[-1] = 0, 16383
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
-    g = _eval_gpu(8, w["mass"], path, "split")[:, :, il]
+    g = _eval_gpu(8, w["mass"], path, "split", launch=launch)[:, :, il]
     assert deriv_error(g[:2], o[:2], mag[:2]).max() <= TOL_FP64
     assert _ok(deriv_error(g, o, mag, nat)[2:], TOL_MIXED[2:])
 

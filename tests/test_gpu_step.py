@@ -265,6 +265,36 @@ def test_batch_matches_oracle(batch_workload, precision):
         assert rel_max(d["v"][:, lo:hi], o.v) <= tol * 10, s
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_full_size_sampled(batch_workload, precision):
+    # all 4096 systems in one launch, as the benchmark runs them (default
+    # persistent grid, graph capture); sampled systems against the oracle:
+    # the largest and the smallest ones (first and last bins) and random ones
+    _say("batch full size %s" % precision)
+    wb = batch_workload
+    offs = wb["offsets"]
+    sizes = np.diff(offs)
+    rng = np.random.default_rng(5)
+    picks = set(rng.choice(len(sizes), 10, replace=False).tolist())
+    picks.update(np.argsort(sizes, kind="stable")[[0, 1, -2, -1]].tolist())
+    bh = BatchHermite(8, offs, precision=precision, device=DEV)
+    st = bh.state(wb["mass"], wb["x"], wb["v"])
+    bh.init(st)
+    steps = 10
+    bh.run(st, wb["dt"], steps, wb["n_iter"])
+    d = st.host()
+    bh.close()
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    for s in sorted(picks):
+        lo, hi = offs[s], offs[s + 1]
+        o = ho.State(wb["mass"][lo:hi], wb["x"][:, lo:hi], wb["v"][:, lo:hi], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, wb["dt"][s], wb["n_iter"])
+        assert rel_max(d["x"][:, lo:hi], o.x) <= tol, (s, sizes[s])
+        assert rel_max(d["v"][:, lo:hi], o.v) <= tol * 10, (s, sizes[s])
+
+
 def test_batch_init_matches_single(batch_workload):
     _say("batch init vs single-system init")
     sub = _subset(batch_workload, np.arange(40))
