@@ -123,11 +123,11 @@ typedef struct {
     double t_comp;         /* compensation term of t (same)                         */
 } hermite_state;
 
-/* Create a context for states of up to n_max particles (n_max >= 0).
+/* Create a context for states of up to n_max particles (0 <= n_max <= 2^40).
  * hip_stream is a hipStream_t (NULL = null stream).  Validates *prm:
  * order -> E_ORDER; precision/corrector out of range, G not finite,
- * eps2 < 0 or not finite, n_max < 0, out NULL -> E_ARG.  Allocates the
- * split-sum workspace for n_max (E_ALLOC on failure). */
+ * eps2 < 0 or not finite, n_max outside [0, 2^40], out NULL -> E_ARG.
+ * Allocates the split-sum workspace for n_max (E_ALLOC on failure). */
 hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hip_stream,
                               hermite_ctx **out);
 
@@ -228,8 +228,10 @@ hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const doubl
                                  int32_t n_steps, int32_t n_iter);
 
 /* The same with an iteration count per system: n_iter_sys is a HOST array
- * [n_sys] of values in 1..64 (E_ARG otherwise), copied to the device before
- * the launch.  A bin of systems iterates as often as its largest count; each
+ * [n_sys] of values in 1..64 (E_ARG otherwise).  It is read during the call
+ * (staged through a pinned buffer of the context), so the caller may change
+ * or free it as soon as the call returns.  A bin of systems iterates as often
+ * as its largest count; each
  * system corrects only its own n times and keeps that iterate (the paper's
  * n-sweep, Sec. 3.1, runs every n side by side this way). */
 hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const double *dt_sys,

@@ -48,6 +48,8 @@ struct hermite_ctx {
     int64_t *d_offsets = nullptr;
     int *d_counter = nullptr;
     int32_t *d_iters = nullptr;   // per-system iteration counts [n_sys]
+    int32_t *h_iters = nullptr;   // their pinned staging copy
+    hipEvent_t iters_copied = nullptr;   // recorded after the staging copy is enqueued
     // ensemble form
     bool ensemble = false;
     hermite::EnsembleCfg *d_cfg = nullptr;
@@ -73,6 +75,10 @@ struct hermite_ctx {
 namespace {
 
 const char *kNoCtxMsg = "hermite: null context";
+
+// Largest n_max accepted: keeps every workspace size (at most a few hundred
+// bytes per body) far from 64-bit overflow.
+constexpr int64_t kMaxBodies = (int64_t)1 << 40;
 
 hermite_status fail(hermite_ctx *ctx, hermite_status st, const std::string &msg)
 {
@@ -228,6 +234,8 @@ void free_ctx(hermite_ctx *ctx)
     if (ctx->d_offsets) (void)hipFree(ctx->d_offsets);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     if (ctx->d_iters) (void)hipFree(ctx->d_iters);
+    if (ctx->h_iters) (void)hipHostFree(ctx->h_iters);
+    if (ctx->iters_copied) (void)hipEventDestroy(ctx->iters_copied);
     if (ctx->d_cfg) (void)hipFree(ctx->d_cfg);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->jrec) (void)hipFree(ctx->jrec);
@@ -278,7 +286,7 @@ hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hi
     *out = nullptr;
     hermite_status st = check_params(prm, msg);
     if (st != HERMITE_OK) return st;
-    if (n_max < 0) return HERMITE_E_ARG;
+    if (n_max < 0 || n_max > kMaxBodies) return HERMITE_E_ARG;
     hermite_ctx *ctx = new hermite_ctx();
     ctx->prm = *prm;
     ctx->p = prm->order / 2 - 1;
@@ -537,12 +545,33 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
     const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {1, 16, 1}};
     int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
     if (s->n > 0) {
-        hipEvent_t e0, e1;
-        HIP_TRY(ctx, hipEventCreate(&e0), "event create");
-        HIP_TRY(ctx, hipEventCreate(&e1), "event create");
+        // the events live until every return below; on failure the previous
+        // launch shape is kept
+        struct Events {
+            hipEvent_t e[2] = {nullptr, nullptr};
+            ~Events()
+            {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } ev;
+        struct Restore {
+            hermite_ctx *c;
+            int ipt, nsplit, jsource, waves;
+            bool keep = false;
+            ~Restore()
+            {
+                if (keep) return;
+                c->ipt = ipt;
+                c->nsplit = nsplit;
+                c->jsource = jsource;
+                c->waves = waves;
+            }
+        } restore{ctx, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves};
+        HIP_TRY(ctx, hipEventCreate(&ev.e[0]), "event create");
+        HIP_TRY(ctx, hipEventCreate(&ev.e[1]), "event create");
         std::vector<Timed> timed;
         for (const Cand &cd : shapes) {
-            if (st != HERMITE_OK) break;
             const hermite::LaunchShape sh{cd.ipt, cd.waves, cd.src ? hermite::JSource::Scalar : hermite::JSource::Lds};
             const int base = hermite::auto_split(s->n, sh, false);
             std::vector<int> cands = {base};
@@ -558,19 +587,20 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
                 ctx->jsource = cd.src;
                 ctx->nsplit = ns;
                 st = hermite_force_derivs(ctx, s);   // warm-up
-                if (st != HERMITE_OK) break;
-                HIP_TRY(ctx, hipEventRecord(e0, ctx->stream), "event record");
-                for (int r = 0; r < 5 && st == HERMITE_OK; ++r) st = hermite_force_derivs(ctx, s);
-                HIP_TRY(ctx, hipEventRecord(e1, ctx->stream), "event record");
-                HIP_TRY(ctx, hipEventSynchronize(e1), "event sync");
+                if (st != HERMITE_OK) return st;
+                HIP_TRY(ctx, hipEventRecord(ev.e[0], ctx->stream), "event record");
+                for (int r = 0; r < 5; ++r) {
+                    st = hermite_force_derivs(ctx, s);
+                    if (st != HERMITE_OK) return st;
+                }
+                HIP_TRY(ctx, hipEventRecord(ev.e[1], ctx->stream), "event record");
+                HIP_TRY(ctx, hipEventSynchronize(ev.e[1]), "event sync");
                 float ms = 0.0f;
-                HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "event time");
-                if (st == HERMITE_OK) timed.push_back({cd, ns, ms});
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.e[0], ev.e[1]), "event time");
+                timed.push_back({cd, ns, ms});
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (st != HERMITE_OK) return st;
+        restore.keep = true;
         // Fastest shape; among those within 2 % of it, the one that writes the
         // fewest split partial sums (then the earliest in the list above).
         float best = 1e30f;
@@ -666,9 +696,16 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
               alloc_copy((void **)&ctx->d_offsets, ctx->offsets.data(), ctx->offsets.size() * sizeof(int64_t)) &&
               alloc_copy((void **)&ctx->d_counter, nullptr, sizeof(int)) &&
               alloc_copy((void **)&ctx->d_iters, nullptr, (size_t)n_sys * sizeof(int32_t)) &&
-              alloc_copy((void **)&ctx->flag, nullptr, sizeof(int));
+              alloc_copy((void **)&ctx->flag, nullptr, sizeof(int)) &&
+              hipHostMalloc((void **)&ctx->h_iters, (size_t)std::max(n_sys, 1) * sizeof(int32_t),
+                            hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         return alloc_failed(ctx);
+    }
+    if (hipEventCreateWithFlags(&ctx->iters_copied, hipEventDisableTiming) != hipSuccess) {
+        clear_hip_error();
+        free_ctx(ctx);
+        return HERMITE_E_HIP;
     }
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
         clear_hip_error();
@@ -728,10 +765,17 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
     if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the batch total");
     if (ctx->n_sys > 0 && !dt_sys) return fail(ctx, HERMITE_E_ARG, "hermite: dt_sys is NULL");
     if (n_steps == 0 || ctx->n_sys == 0) return HERMITE_OK;
-    if (iters_host)
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_iters, iters_host, (size_t)ctx->n_sys * sizeof(int32_t),
+    if (iters_host) {
+        // The counts are read here, into the pinned staging buffer, once the
+        // previous call's copy out of it has run; the caller's array is free
+        // again when this call returns.
+        HIP_TRY(ctx, hipEventSynchronize(ctx->iters_copied), "per-system n_iter staging wait");
+        std::memcpy(ctx->h_iters, iters_host, (size_t)ctx->n_sys * sizeof(int32_t));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_iters, ctx->h_iters, (size_t)ctx->n_sys * sizeof(int32_t),
                                     hipMemcpyHostToDevice, ctx->stream),
                 "per-system n_iter copy");
+        HIP_TRY(ctx, hipEventRecord(ctx->iters_copied, ctx->stream), "per-system n_iter event");
+    }
     int wg = ctx->batch_workgroups;
     if (wg <= 0) wg = std::min<int>(ctx->n_bins, 256 * 8);
     const bool per_system = iters_host != nullptr;

@@ -47,7 +47,7 @@ def _create(**kw):
     (dict(order=5), -2), (dict(order=10), -2), (dict(order=0), -2),
     (dict(precision=3), -1), (dict(corrector=3), -1), (dict(corrector=-1), -1),
     (dict(eps2=-1e-9), -1), (dict(eps2=float("nan")), -1), (dict(G=float("inf")), -1),
-    (dict(n_max=-1), -1), (dict(compensated=2), -1), (dict(compensated=-1), -1),
+    (dict(n_max=-1), -1), (dict(n_max=(1 << 40) + 1), -1), (dict(compensated=2), -1), (dict(compensated=-1), -1),
 ])
 def test_create_rejects_bad_params(kw, code):
     st, ctx = _create(**kw)
