@@ -32,8 +32,8 @@ FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
 # Sources that define the evaluation kernels; the measured HBM traffic below
 # is reported only while their hash and the launch shape (which fixes the
 # split workspace) match what was profiled.
-KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/pair_chain.h",
-                  "paper_2006_02501_amd/csrc/force_launch.h"]
+KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/sym_kernels.hip",
+                  "paper_2006_02501_amd/csrc/pair_chain.h", "paper_2006_02501_amd/csrc/force_launch.h"]
 # HBM bytes per evaluation launch (force kernel + split reduction), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
@@ -72,9 +72,20 @@ MEASURED_TRAFFIC = {
         "write_bytes": 104254669
     }
 }
+# j_source codes of hermite_set_launch: LDS tiles, scalar stream, every pair once
+JSOURCES = ["lds", "scalar", "pairs"]
 # MI355X published vector peaks: 256 CUs x 4 SIMD16 x 2 flops (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s FP64; FP32 twice that (157.3) with packed-FP32 issue.
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "split": 78.6}
+
+
+def eval_kernel_name(launch):
+    """The kernels of one 8th-order FP64 evaluation in the given launch shape."""
+    if launch and launch["j_source"] == "pairs":
+        return "force_pairs_kernel<K=3> (every pair once) + partial-sum reduction (one evaluation)"
+    if launch and launch["j_source"] == "scalar":
+        return "pack_j_kernel + force_stream_kernel<K=3, FP64> + split reduction (one evaluation)"
+    return "force_kernel<K=3, FP64> + split reduction (one evaluation)"
 
 
 def log(*a):
@@ -160,7 +171,7 @@ def time_mode(precision, w, steps, warmup, autotune=True, launch=None):
         eval_ms_avg=avg_eval_s * 1e3,
         eval_ms_median=float(np.median(eval_ms)),
         eval_interactions_per_s=inter / avg_eval_s,
-        launch=({"i_per_thread": shape[0], "j_split": shape[1], "j_source": ["lds", "scalar"][shape[2]],
+        launch=({"i_per_thread": shape[0], "j_split": shape[1], "j_source": JSOURCES[shape[2]],
                  "wg_waves": shape[3]} if shape else None),
         energy_rel_change=(E1 - E0) / abs(E0),
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
@@ -557,7 +568,7 @@ def main():
                                "8th-order modified Hermite, P(EC)^3, dt=2pi/2000, G=1, eps=0",
                    "n_bodies": n, "order": 8, "n_iter": 3},
         "roofline": dict(r["roofline"],
-                         kernel="force_kernel<K=3, FP64> + split reduction (one evaluation)",
+                         kernel=eval_kernel_name(r["launch"]),
                          flops_per_interaction=FLOPS_PER_INTERACTION[8],
                          algorithmic_bytes=(13 + 12) * 8 * n),
         "fp64": {k: v for k, v in r.items() if k != "roofline"},
@@ -578,7 +589,7 @@ def main():
     if not args.no_variable_step:
         log("  variable step ...")
         lf = r["launch"]
-        shape = (lf["i_per_thread"], lf["j_split"], 0 if lf["j_source"] == "lds" else 1, lf["wg_waves"]) if lf else None
+        shape = (lf["i_per_thread"], lf["j_split"], JSOURCES.index(lf["j_source"]), lf["wg_waves"]) if lf else None
         vs = variable_step(w, args.steps, args.warmup, args.eta, shape)
         vs["over_fixed_step_ms"] = vs["ms_per_step"] / r["ms_per_step"]
         out["variable_step"] = vs

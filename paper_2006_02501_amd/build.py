@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhermite.so")
-SOURCES = ["force_kernels.hip", "step_kernels.hip", "timestep_kernels.hip", "batch_kernel.hip",
+SOURCES = ["force_kernels.hip", "sym_kernels.hip", "step_kernels.hip", "timestep_kernels.hip", "batch_kernel.hip",
            "ensemble_kernels.hip", "runtime.cpp"]
 ARCH = "gfx950"
 

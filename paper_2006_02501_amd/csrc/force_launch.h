@@ -14,8 +14,10 @@ constexpr int kMaxPath = 6;   // path derivatives x^(0..5) (generic initialisati
 enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2, Split = 3 };
 
 // Where the evaluation reads the j-particles from: LDS tiles filled by the
-// workgroup, or packed records streamed through the scalar unit into SGPRs.
-enum class JSource { Lds = 0, Scalar = 1 };
+// workgroup, or packed records streamed through the scalar unit into SGPRs;
+// or Pairs: every pair once, for both of its bodies (FP64 chain only,
+// N <= kPairsMaxN; see launch_force_pairs).
+enum class JSource { Lds = 0, Scalar = 1, Pairs = 2 };
 
 struct ForceArgs {
     int64_t n;                    // particles (i and j range over all of them)
@@ -39,9 +41,9 @@ struct ForceArgs {
 // Launch shape of the FP64 / mixed evaluation (the generic initialisation
 // chain always uses 4-wave workgroups with one i-particle per lane).
 struct LaunchShape {
-    int ipt;          // i-particles per lane: 1 or 2
+    int ipt;          // i-particles per lane: 1..4
     int waves;        // waves per workgroup: 4 or 16 (16 with ipt = 1 only)
-    JSource jsource;  // LDS tiles or scalar stream
+    JSource jsource;  // LDS tiles, scalar stream, or every pair once
 };
 
 // Doubles per particle of the packed j-stream.
@@ -52,5 +54,14 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &shap
 
 // j-split count the evaluation uses when the caller does not fix one.
 int auto_split(int64_t n, const LaunchShape &shape, bool generic);
+
+// Every-pair-once evaluation (FP64, K = 1..3, k_first = 0): work items are
+// pairs of 256-body super-blocks, each writing 2 * (K+1) * 3 * 256 partial
+// sums into a.partial, which a fixed-order reduction adds into a.out.  With
+// a.qpart, one pair-rate maximum per item (a.q_count = the item count).
+constexpr int64_t kPairsMaxN = 32768;
+int64_t pairs_items(int64_t n);
+int64_t pairs_partial_doubles(int64_t n, int K);
+hipError_t launch_force_pairs(const ForceArgs &a, hipStream_t st);
 
 }  // namespace hermite

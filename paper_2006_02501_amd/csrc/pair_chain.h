@@ -101,6 +101,65 @@ __device__ __forceinline__ void chain_accumulate(const T (&r)[3], const T (&v)[3
     }
 }
 
+// One pair taken once for both of its bodies (FP64): the chain's vectors
+// (r, J', S', C') are odd under the exchange of i and j (every relative path
+// derivative changes sign, alpha, beta and gamma do not), so body i adds
+// G m_j w^(-3/2) times them and body j adds -G m_i w^(-3/2) times them.
+// mj3 = G m_j w^(-3/2), nmi3 = -G m_i w^(-3/2), rinv2 = 1/w.
+template <int K>
+__device__ __forceinline__ void chain_pair(const double (&r)[3], const double (&v)[3], const double (&a)[3],
+                                           const double (&j)[3], double mj3, double nmi3, double rinv2,
+                                           double (&acc_i)[K + 1][3], double (&acc_j)[K + 1][3])
+{
+    static_assert(K >= 1 && K <= 3, "chain supports 1..3 derivatives");
+    const double rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
+    const double alpha = rv * rinv2;
+    double vv = 0.0, ra = 0.0, va = 0.0, rj = 0.0;
+    if constexpr (K >= 2) {
+        vv = fma_t(v[2], v[2], fma_t(v[1], v[1], v[0] * v[0]));
+        ra = fma_t(r[2], a[2], fma_t(r[1], a[1], r[0] * a[0]));
+    }
+    if constexpr (K >= 3) {
+        va = fma_t(v[2], a[2], fma_t(v[1], a[1], v[0] * a[0]));
+        rj = fma_t(r[2], j[2], fma_t(r[1], j[1], r[0] * j[0]));
+    }
+    const double n1 = -3.0 * alpha;
+    double J[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc_i[0][c] = fma_t(mj3, r[c], acc_i[0][c]);
+        acc_j[0][c] = fma_t(nmi3, r[c], acc_j[0][c]);
+        J[c] = fma_t(n1, r[c], v[c]);
+        acc_i[1][c] = fma_t(mj3, J[c], acc_i[1][c]);
+        acc_j[1][c] = fma_t(nmi3, J[c], acc_j[1][c]);
+    }
+    if constexpr (K >= 2) {
+        const double alpha2 = alpha * alpha;
+        const double beta = fma_t(vv + ra, rinv2, alpha2);
+        const double n2 = 2.0 * n1;
+        const double n3 = -3.0 * beta;
+        double S[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            S[c] = fma_t(n3, r[c], fma_t(n2, J[c], a[c]));
+            acc_i[2][c] = fma_t(mj3, S[c], acc_i[2][c]);
+            acc_j[2][c] = fma_t(nmi3, S[c], acc_j[2][c]);
+        }
+        if constexpr (K >= 3) {
+            const double gamma = fma_t(fma_t(3.0, va, rj), rinv2, alpha * fma_t(-4.0, alpha2, -1.0 * n3));
+            const double n4 = 3.0 * n1;
+            const double n5 = 3.0 * n3;
+            const double n6 = -3.0 * gamma;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double C = fma_t(n6, r[c], fma_t(n5, J[c], fma_t(n4, S[c], j[c])));
+                acc_i[3][c] = fma_t(mj3, C, acc_i[3][c]);
+                acc_j[3][c] = fma_t(nmi3, C, acc_j[3][c]);
+            }
+        }
+    }
+}
+
 // Split precision (Sec. 4: lower precision for the higher derivatives only):
 // a and adot exactly as chain_accumulate<K, double> forms them (the same
 // operations, so the same bits), a^(2) and a^(3) in FP32 from the FP32 casts

@@ -166,7 +166,18 @@ int64_t partial_capacity(int64_t n_max, int p)
     const int64_t nv = p + 1;
     int64_t ns = ((int64_t)4 << 20) / n_max;
     ns = std::max<int64_t>(4, std::min<int64_t>(64, ns));
-    return nv * 3 * n_max * ns;
+    int64_t cap = nv * 3 * n_max * ns;
+    // and the every-pair-once partials (at most 2 * 12 * 256 doubles for each
+    // of the ~n^2 / 131072 super-block pairs)
+    if (n_max <= hermite::kPairsMaxN) cap = std::max(cap, hermite::pairs_partial_doubles(n_max, p));
+    return cap;
+}
+
+// The every-pair-once evaluation of n bodies fits this context's workspace.
+bool pairs_fit(const hermite_ctx *ctx, int64_t n)
+{
+    return n <= hermite::kPairsMaxN && hermite::pairs_partial_doubles(n, ctx->p) <= ctx->partial_cap &&
+           hermite::pairs_items(n) <= ctx->qpart_cap;
 }
 
 hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
@@ -190,7 +201,12 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
         a.qpart_cap = ctx->qpart_cap;
         a.q_count = q_count;
     }
-    hermite::LaunchShape sh{ipt, waves, jsource == 1 ? hermite::JSource::Scalar : hermite::JSource::Lds};
+    const hermite::JSource src = jsource == 2 ? hermite::JSource::Pairs
+                                 : jsource == 1 ? hermite::JSource::Scalar
+                                                : hermite::JSource::Lds;
+    hermite::LaunchShape sh{ipt, waves, src};
+    if (src == hermite::JSource::Pairs && (chain != Chain::Fp64 || !pairs_fit(ctx, s->n)))
+        return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation needs FP64 and n <= 32768");
     if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
     HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
     return HERMITE_OK;
@@ -333,7 +349,11 @@ hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_
         return fail(ctx, HERMITE_E_ARG,
                     "hermite: 3 or 4 i-particles per lane need the scalar j-source and 4-wave workgroups");
     if (j_split < 0 || j_split > 64) return fail(ctx, HERMITE_E_ARG, "hermite: j_split must be in 0..64");
-    if (j_source != 0 && j_source != 1) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0 or 1");
+    if (j_source < 0 || j_source > 2) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0, 1 or 2");
+    if (j_source == 2 && (i_per_thread != 1 || wg_waves != 4 || ctx->prm.precision != HERMITE_FP64))
+        return fail(ctx, HERMITE_E_ARG,
+                    "hermite: the every-pair-once evaluation (j_source 2) is FP64 with one i-particle per lane "
+                    "and 4-wave workgroups");
     if (wg_waves != 4 && wg_waves != 16) return fail(ctx, HERMITE_E_ARG, "hermite: wg_waves must be 4 or 16");
     if (wg_waves == 16 && (i_per_thread != 1 || j_source != 1))
         return fail(ctx, HERMITE_E_ARG,
@@ -541,8 +561,9 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
         Cand c;
         int split;
         float ms;
+        int64_t partials;   // partial sums the shape writes per evaluation (doubles)
     };
-    const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {1, 16, 1}};
+    const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {1, 16, 1}, {1, 4, 2}};
     int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
     if (s->n > 0) {
         // the events live until every return below; on failure the previous
@@ -572,15 +593,23 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
         HIP_TRY(ctx, hipEventCreate(&ev.e[1]), "event create");
         std::vector<Timed> timed;
         for (const Cand &cd : shapes) {
-            const hermite::LaunchShape sh{cd.ipt, cd.waves, cd.src ? hermite::JSource::Scalar : hermite::JSource::Lds};
-            const int base = hermite::auto_split(s->n, sh, false);
-            std::vector<int> cands = {base};
-            for (int f : {2, 4}) {
-                if (base * f <= 64) cands.push_back(base * f);
-                if (base / f >= 1) cands.push_back(base / f);
+            std::vector<int> cands;
+            if (cd.src == 2) {
+                // every pair once: FP64, when its partial sums fit; no j-split
+                if (ctx->prm.precision != HERMITE_FP64 || !pairs_fit(ctx, s->n)) continue;
+                cands = {0};
+            } else {
+                const hermite::LaunchShape sh{cd.ipt, cd.waves,
+                                              cd.src ? hermite::JSource::Scalar : hermite::JSource::Lds};
+                const int base = hermite::auto_split(s->n, sh, false);
+                cands = {base};
+                for (int f : {2, 4}) {
+                    if (base * f <= 64) cands.push_back(base * f);
+                    if (base / f >= 1) cands.push_back(base / f);
+                }
+                std::sort(cands.begin(), cands.end());
+                cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
             }
-            std::sort(cands.begin(), cands.end());
-            cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
             for (int ns : cands) {
                 ctx->ipt = cd.ipt;
                 ctx->waves = cd.waves;
@@ -597,18 +626,22 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
                 HIP_TRY(ctx, hipEventSynchronize(ev.e[1]), "event sync");
                 float ms = 0.0f;
                 HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.e[0], ev.e[1]), "event time");
-                timed.push_back({cd, ns, ms});
+                const int64_t per_split = (int64_t)(ctx->p + 1) * 3 * s->n;
+                const int64_t partials = cd.src == 2 ? hermite::pairs_partial_doubles(s->n, ctx->p)
+                                         : ns > 1    ? (int64_t)ns * per_split
+                                                     : 0;
+                timed.push_back({cd, ns, ms, partials});
             }
         }
         restore.keep = true;
         // Fastest shape; among those within 2 % of it, the one that writes the
-        // fewest split partial sums (then the earliest in the list above).
+        // fewest partial sums (then the earliest in the list above).
         float best = 1e30f;
         for (const Timed &t : timed) best = std::min(best, t.ms);
         const Timed *pick = nullptr;
         for (const Timed &t : timed) {
             if (t.ms > 1.02f * best) continue;
-            if (!pick || t.split < pick->split) pick = &t;
+            if (!pick || t.partials < pick->partials) pick = &t;
         }
         if (pick) {
             best_ipt = pick->c.ipt;

@@ -1,0 +1,248 @@
+// O(N^2) evaluation with every pair taken once (FP64): the pair's chain
+// serves both bodies (Newton's third law extended to the derivatives: the
+// vectors r, J', S', C' change sign under i <-> j, the scalars alpha, beta,
+// gamma do not), so the chain runs N (N - 1) / 2 times instead of N (N - 1).
+//
+// Work items are pairs (I, J), I <= J, of super-blocks of 256 bodies; one
+// workgroup of 4 wave64 per item.  Wave w keeps the 64 bodies of i-block w of
+// super-block I (path and running sums) in VGPRs.  The j super-block is staged
+// in LDS (structure of arrays, G m then the path components).  In phase s,
+// wave w sweeps j-block v = (w + s) mod 4: at sweep step t lane l pairs its
+// body with j-body (l + t) mod 64, and the j-body's running sum travels with
+// it: after every step the j-sums move one lane down (DPP wave rotate), so the
+// lane that handles a j-body next step holds its sum.  After the sweep the
+// wave adds its j-sums into the LDS sums of block v, which no other wave
+// touches in that phase (the phases form a Latin square); a barrier separates
+// the phases.  On the diagonal item (I = J) each unordered pair of blocks is
+// visited once (phases 0, 1, and 2 for waves 0 and 1 only), and inside a
+// block each unordered pair of bodies once (steps 1..32, step 32 on lanes
+// 0..31 only).
+//
+// Outputs per item: the i-side sums of super-block I and the j-side sums of
+// super-block J (partial sums in HBM); a second kernel adds, for every body,
+// the partials of the items that hold it, in a fixed order.  No atomics:
+// the result is bitwise reproducible.  The partials take 2 * 12 * 256 doubles
+// per item, about N^2 / 2700 doubles in all (100 MB at N = 16384), so this
+// path is offered for N up to kPairsMaxN.
+#include "force_launch.h"
+#include "pair_chain.h"
+
+namespace hermite {
+namespace {
+
+constexpr int kPW = 4;             // waves per workgroup = j-blocks per super-block
+constexpr int kPL = 64;            // lanes per wave = bodies per block
+constexpr int kPS = kPW * kPL;     // bodies per super-block
+
+template <int K>
+struct PPath {
+    const double *p[K + 1];
+};
+
+// The j-body's running sum moves one lane down: lane l receives lane l + 1's
+// value (lane 63 receives lane 0's).  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_down(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Item k -> (I, J): the NS (NS - 1) / 2 off-diagonal items first, row by
+// row, then the NS diagonal ones (they carry ~5/8 of an item's work and end
+// the launch).
+__device__ __forceinline__ void item_pair(int64_t k, int ns, int &I, int &J)
+{
+    const int64_t offd = (int64_t)ns * (ns - 1) / 2;
+    if (k >= offd) {
+        I = J = (int)(k - offd);
+        return;
+    }
+    int i = 0;
+    int64_t off = 0;
+    while (off + (ns - 1 - i) <= k) {
+        off += ns - 1 - i;
+        ++i;
+    }
+    I = i;
+    J = i + 1 + (int)(k - off);
+}
+
+__device__ __forceinline__ int64_t item_index(int I, int J, int ns)
+{
+    if (I == J) return (int64_t)ns * (ns - 1) / 2 + I;
+    return (int64_t)I * (ns - 1) - (int64_t)I * (I - 1) / 2 + (J - I - 1);
+}
+
+template <int K, bool QM>
+__global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
+                                                          double G, double eps2, int ns, double *__restrict__ part,
+                                                          double *__restrict__ qpart)
+{
+    constexpr int NV = (K + 1) * 3;
+    __shared__ double sj[NV + 1][kPS];   // j super-block: G m, then x, v, (a, adot) components
+    __shared__ double jsum[NV][kPS];     // j-side sums of the item
+    __shared__ double wq[kPW];
+    const int tid = threadIdx.x;
+    const int w = tid / kPL, l = tid % kPL;
+    int I, J;
+    item_pair(blockIdx.x, ns, I, J);
+    const bool diag = I == J;
+
+    const int64_t jg = (int64_t)J * kPS + tid;
+    const bool jok = jg < n;
+    sj[0][tid] = jok ? G * mass[jg] : 0.0;
+#pragma unroll
+    for (int k = 0; k <= K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sj[1 + 3 * k + c][tid] = jok ? path.p[k][c * n + jg] : 0.0;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) jsum[e][tid] = 0.0;
+
+    const int64_t ig = (int64_t)I * kPS + tid;
+    const bool iok = ig < n;
+    const double gmi = iok ? G * mass[ig] : 0.0;
+    double xi[K + 1][3], acc_i[K + 1][3];
+#pragma unroll
+    for (int k = 0; k <= K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xi[k][c] = iok ? path.p[k][c * n + ig] : 0.0;
+            acc_i[k][c] = 0.0;
+        }
+    double qmax = 0.0;
+    // j-bodies of super-block J that exist
+    const int jvalid = (int)min((int64_t)kPS, n - (int64_t)J * kPS);
+    __syncthreads();
+
+    const int nphase = diag ? 3 : kPW;
+    for (int s = 0; s < nphase; ++s) {
+        const int v = (w + s) % kPW;
+        const bool same = diag && s == 0;                 // the wave's own block
+        if (!(diag && s == 2 && w >= 2)) {                // wave-uniform
+            double acc_j[K + 1][3];
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc_j[k][c] = 0.0;
+            const int t0 = same ? 1 : 0, t1 = same ? kPL / 2 : kPL - 1;
+            for (int t = t0; t <= t1; ++t) {
+                const int js = v * kPL + ((l + t) & (kPL - 1));
+                const bool ok = iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2);
+                double r[3], vv[3], a[3], jk[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = sj[1 + c][js] - xi[0][c];
+                    vv[c] = sj[4 + c][js] - xi[1][c];
+                    if constexpr (K >= 2) a[c] = sj[7 + c][js] - xi[2][c]; else a[c] = 0.0;
+                    if constexpr (K >= 3) jk[c] = sj[10 + c][js] - xi[3][c]; else jk[c] = 0.0;
+                }
+                double w2 = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                w2 = ok ? w2 : 1.0;
+                const double rinv = rsqrt64(w2);
+                const double rinv2 = rinv * rinv;
+                const double q3 = ok ? rinv * rinv2 : 0.0;
+                const double gmj = sj[0][js];
+                if constexpr (QM) qmax = __builtin_fmax(qmax, (gmi + gmj) * q3);
+                chain_pair<K>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j);
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc_j[k][c] = lane_down(acc_j[k][c]);
+            }
+            // lane l now holds the sums of j-body (l + t1 + 1) mod 64 of block v
+            const int js_end = v * kPL + ((l + t1 + 1) & (kPL - 1));
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) jsum[3 * k + c][js_end] += acc_j[k][c];
+        }
+        __syncthreads();
+    }
+
+    // partials of this item: [2][NV][kPS], side 0 = super-block I, 1 = J
+    double *pi = part + (int64_t)blockIdx.x * 2 * NV * kPS;
+#pragma unroll
+    for (int k = 0; k <= K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pi[(3 * k + c) * kPS + tid] = acc_i[k][c];
+            pi[(NV + 3 * k + c) * kPS + tid] = jsum[3 * k + c][tid];
+        }
+    if constexpr (QM) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) qmax = __builtin_fmax(qmax, __shfl_xor(qmax, off, 64));
+        if (l == 0) wq[w] = qmax;
+        __syncthreads();
+        if (tid == 0) {
+            double q = wq[0];
+#pragma unroll
+            for (int k = 1; k < kPW; ++k) q = __builtin_fmax(q, wq[k]);
+            qpart[blockIdx.x] = q;
+        }
+    }
+}
+
+// Every body's sums: the i-side partials of the items (Kb, J), J = Kb..NS-1,
+// then the j-side partials of the items (I, Kb), I = 0..Kb, in that order.
+__global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__restrict__ part,
+                                    double *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nv * n) return;
+    const int comp = (int)(e / n);
+    const int64_t b = e - (int64_t)comp * n;
+    const int kb = (int)(b / kPS), loc = (int)(b % kPS);
+    const int64_t stride = (int64_t)2 * nv * kPS;
+    double s = 0.0;
+    for (int J = kb; J < ns; ++J) s += part[item_index(kb, J, ns) * stride + (int64_t)comp * kPS + loc];
+    for (int I = 0; I <= kb; ++I) s += part[item_index(I, kb, ns) * stride + (int64_t)(nv + comp) * kPS + loc];
+    out[e] = s;
+}
+
+template <int K, bool QM>
+hipError_t launch_k(const ForceArgs &a, hipStream_t st)
+{
+    PPath<K> path;
+    for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
+    const int ns = (int)((a.n + kPS - 1) / kPS);
+    const int64_t items = pairs_items(a.n);
+    hipLaunchKernelGGL((force_pairs_kernel<K, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass, path, a.G,
+                       a.eps2, ns, a.partial, a.qpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nv = (K + 1) * 3;
+    const int64_t cnt = (int64_t)nv * a.n;
+    hipLaunchKernelGGL(reduce_pairs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n, nv, ns,
+                       (const double *)a.partial, a.out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t pairs_items(int64_t n)
+{
+    const int64_t ns = (n + kPS - 1) / kPS;
+    return ns * (ns + 1) / 2;
+}
+
+int64_t pairs_partial_doubles(int64_t n, int K) { return pairs_items(n) * 2 * (K + 1) * 3 * kPS; }
+
+hipError_t launch_force_pairs(const ForceArgs &a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (a.k_first != 0 || a.K < 1 || a.K > 3 || a.n > kPairsMaxN) return hipErrorInvalidValue;
+    if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
+    const bool qm = a.qpart != nullptr;
+    if (qm) {
+        if (pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
+        if (a.q_count) *a.q_count = (int)pairs_items(a.n);
+    }
+    switch (a.K) {
+        case 1: return qm ? launch_k<1, true>(a, st) : launch_k<1, false>(a, st);
+        case 2: return qm ? launch_k<2, true>(a, st) : launch_k<2, false>(a, st);
+        default: return qm ? launch_k<3, true>(a, st) : launch_k<3, false>(a, st);
+    }
+}
+
+}  // namespace hermite

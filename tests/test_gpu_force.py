@@ -86,6 +86,60 @@ def test_force_derivs_launch_shapes(order, shape, source):
     assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
 
 
+PAIRS = (1, 0, 2, 4)   # every pair once (j_source 2)
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 255, 256, 257, 511, 700, 1000, 2050])
+def test_force_derivs_pairs_once(order, n):
+    # every pair taken once for both bodies: ragged n over one and several
+    # 256-body super-blocks (diagonal and off-diagonal items, partial blocks)
+    _say("force_derivs pairs-once order=%d n=%d" % (order, n))
+    p = order // 2 - 1
+    w, path = disc_path(n, p)
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, w["mass"], path, "fp64", launch=PAIRS)
+    assert deriv_error(g, o, mag).max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_force_derivs_pairs_once_softened_and_reproducible(order):
+    _say("force_derivs pairs-once softened order=%d" % order)
+    rng = np.random.default_rng(10 + order)
+    p = order // 2 - 1
+    n = 1531
+    mass, path = random_path(rng, n, p)
+    o, mag, nat = ho.pair_derivs(mass, path, K=p, eps2=1e-4, G=0.7, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, mass, path, "fp64", eps2=1e-4, G=0.7, launch=PAIRS)
+    assert deriv_error(g, o, mag).max() <= TOL_FP64
+    assert np.array_equal(g, _eval_gpu(order, mass, path, "fp64", eps2=1e-4, G=0.7, launch=PAIRS))
+
+
+def test_pairs_once_limits():
+    _say("pairs-once limits")
+    from paper_2006_02501_amd import HermiteError
+    for prec in ("mixed", "split"):
+        h = Hermite(8, 16, precision=prec, device=DEV)
+        with pytest.raises(HermiteError):
+            h.set_launch(*PAIRS)
+        h.close()
+    h = Hermite(8, 16, device=DEV)
+    for bad in [(2, 0, 2, 4), (1, 0, 2, 16)]:
+        with pytest.raises(HermiteError):
+            h.set_launch(*bad)
+    h.close()
+    # above 32768 bodies the evaluation refuses the shape (E_ARG), in-range it runs
+    n = 32769
+    rng = np.random.default_rng(3)
+    h = Hermite(4, n, device=DEV)
+    st = h.state(np.full(n, 1.0 / n), rng.normal(size=(3, n)), np.zeros((3, n)))
+    h.set_launch(*PAIRS)
+    with pytest.raises(HermiteError) as ei:
+        h.force_derivs(st)
+    assert ei.value.status == -1
+    h.close()
+
+
 def test_set_launch_validation():
     h = Hermite(8, 16, device=DEV)
     from paper_2006_02501_amd import HermiteError
@@ -124,6 +178,7 @@ def test_force_derivs_bitwise_reproducible():
 # benchmark's autotuner picks on the 16k disc and that its traffic profile
 # was taken with.
 BENCH_SHAPES = {"fp64": (2, 4, 0, 4), "mixed": (1, 64, 1, 4), "split": (1, 64, 1, 4)}
+
 
 
 def _eval_autotuned(order, mass, path, precision):

@@ -12,7 +12,7 @@ import torch
 
 from oracle import hermite_oracle as ho
 from paper_2006_02501_amd import Hermite, HermiteError
-from parity_util import TOL_MIXED, rel_max
+from parity_util import TOL_MIXED, disc_path, rel_max
 from workloads import disc100, kepler_two_body
 
 pytestmark = pytest.mark.gpu
@@ -165,6 +165,28 @@ def test_fused_rate_in_every_launch_shape(launch, precision):
     h.close()
     if precision == "fp64":
         assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
+
+
+@pytest.mark.parametrize("nb", [101, 700])
+def test_fused_rate_pairs_once(nb):
+    # the every-pair-once evaluation takes the pair rate along too (one
+    # maximum per super-block pair): the same steps as the oracle's
+    _say("fused rate pairs-once n=%d" % nb)
+    w = disc100() if nb == 101 else dict(disc_path(nb, 1)[0], eps2=1e-8)
+    eps2 = w["eps2"]
+    o = ho.State(w["mass"], w["x"], w["v"], 3)
+    ho.init_derivs(o, eps2=eps2)
+    h = Hermite(8, len(w["mass"]), eps2=eps2, device=DEV)
+    h.set_launch(1, 0, 2, 4)
+    st = h.state(w["mass"], w["x"], w["v"])
+    h.init(st)
+    for _ in range(3):
+        do = ho.step_symmetric(o, 0.08, 3, eps2=eps2)
+        dg = h.step_symmetric(st, 0.08, 3)
+        assert abs(dg / do - 1.0) <= 1e-13, (dg, do)
+    g = st.host()
+    h.close()
+    assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
 
 
 def test_mixed_symmetric_step_within_force_bound():
