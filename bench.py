@@ -34,42 +34,43 @@ FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
 # split workspace) match what was profiled.
 KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/sym_kernels.hip",
                   "paper_2006_02501_amd/csrc/pair_chain.h", "paper_2006_02501_amd/csrc/force_launch.h"]
-# HBM bytes per evaluation launch (force kernel + split reduction), from
+# HBM bytes per evaluation (evaluation kernel and its reduction, plus the
+# j-record packing of the scalar source), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "ed3ad607e440d2d3d11253f403ce5a7095e3976bde5a266af70348456fbc16d5",
+        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
         "launch": {
-            "i_per_thread": 2,
-            "j_split": 4,
-            "j_source": "lds",
+            "i_per_thread": 1,
+            "j_split": 0,
+            "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 20770384,
-        "write_bytes": 7785677
+        "fetch_bytes": 124782214,
+        "write_bytes": 103809024
     },
     "mixed": {
-        "sources_sha256": "ed3ad607e440d2d3d11253f403ce5a7095e3976bde5a266af70348456fbc16d5",
+        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
         "launch": {
             "i_per_thread": 1,
             "j_split": 64,
             "j_source": "scalar",
             "wg_waves": 4
         },
-        "fetch_bytes": 128792914,
-        "write_bytes": 104254669
+        "fetch_bytes": 137600524,
+        "write_bytes": 104333312
     },
     "split": {
-        "sources_sha256": "ed3ad607e440d2d3d11253f403ce5a7095e3976bde5a266af70348456fbc16d5",
+        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
         "launch": {
             "i_per_thread": 1,
             "j_split": 64,
             "j_source": "scalar",
             "wg_waves": 4
         },
-        "fetch_bytes": 128792402,
-        "write_bytes": 104254669
+        "fetch_bytes": 137599714,
+        "write_bytes": 104333312
     }
 }
 # j_source codes of hermite_set_launch: LDS tiles, scalar stream, every pair once
