@@ -294,7 +294,13 @@ hermite_status hermite_ensemble_run(hermite_ctx *ctx, hermite_state *s, const he
  *                  n * 64 <= 4 Mi and at least 4 at any n <= n_max)
  *   j_source       0: j-particles staged through LDS tiles by each workgroup;
  *                  1: j-particles packed once per evaluation into 128-byte
- *                  records and streamed through the scalar unit into SGPRs
+ *                  records and streamed through the scalar unit into SGPRs;
+ *                  2: every pair evaluated once for both of its bodies (the
+ *                  chain's vectors change sign under i <-> j), with
+ *                  i_per_thread 1 and wg_waves 4, j_split ignored; for
+ *                  n <= 32768 (hermite_force_derivs returns E_ARG above),
+ *                  partial sums in the context's workspace, added in a fixed
+ *                  order
  *   wg_waves       4 or 16 wave64 per workgroup; 16 (scalar source and one
  *                  i-particle per lane only): the waves share 64 i-particles
  *                  and split the j-range among themselves, adding their sums

@@ -684,8 +684,8 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, 
     const bool generic = chain == Chain::Generic;
     if (!generic && (a.k_first != 0 || a.K > 3)) return hipErrorInvalidValue;
     if (sh.jsource == JSource::Pairs) {
-        if (chain != Chain::Fp64 || sh.ipt != 1 || sh.waves != 4) return hipErrorInvalidValue;
-        return launch_force_pairs(a, st);
+        if (generic || sh.ipt != 1 || sh.waves != 4) return hipErrorInvalidValue;
+        return launch_force_pairs(a, chain, st);
     }
     if (!generic && sh.jsource == JSource::Scalar && !a.jrec) return hipErrorInvalidValue;
     const int64_t per_split = (int64_t)nv * 3 * a.n;

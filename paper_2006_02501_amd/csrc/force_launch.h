@@ -15,8 +15,8 @@ enum class Chain { Fp64 = 0, Mixed = 1, Generic = 2, Split = 3 };
 
 // Where the evaluation reads the j-particles from: LDS tiles filled by the
 // workgroup, or packed records streamed through the scalar unit into SGPRs;
-// or Pairs: every pair once, for both of its bodies (FP64 chain only,
-// N <= kPairsMaxN; see launch_force_pairs).
+// or Pairs: every pair once, for both of its bodies (FP64, mixed and split
+// chains, N <= kPairsMaxN; see launch_force_pairs).
 enum class JSource { Lds = 0, Scalar = 1, Pairs = 2 };
 
 struct ForceArgs {
@@ -55,13 +55,14 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &shap
 // j-split count the evaluation uses when the caller does not fix one.
 int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 
-// Every-pair-once evaluation (FP64, K = 1..3, k_first = 0): work items are
-// pairs of 256-body super-blocks, each writing 2 * (K+1) * 3 * 256 partial
-// sums into a.partial, which a fixed-order reduction adds into a.out.  With
-// a.qpart, one pair-rate maximum per item (a.q_count = the item count).
+// Every-pair-once evaluation (FP64, mixed or split chain, K = 1..3,
+// k_first = 0): work items are pairs of 256-body super-blocks, each writing
+// 2 * (K+1) * 3 * 256 partial sums into a.partial, which a fixed-order
+// reduction adds into a.out.  With a.qpart (FP64 and split chains), one
+// pair-rate maximum per item (a.q_count = the item count).
 constexpr int64_t kPairsMaxN = 32768;
 int64_t pairs_items(int64_t n);
 int64_t pairs_partial_doubles(int64_t n, int K);
-hipError_t launch_force_pairs(const ForceArgs &a, hipStream_t st);
+hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st);
 
 }  // namespace hermite

@@ -101,20 +101,20 @@ __device__ __forceinline__ void chain_accumulate(const T (&r)[3], const T (&v)[3
     }
 }
 
-// One pair taken once for both of its bodies (FP64): the chain's vectors
+// One pair taken once for both of its bodies: the chain's vectors
 // (r, J', S', C') are odd under the exchange of i and j (every relative path
 // derivative changes sign, alpha, beta and gamma do not), so body i adds
 // G m_j w^(-3/2) times them and body j adds -G m_i w^(-3/2) times them.
-// mj3 = G m_j w^(-3/2), nmi3 = -G m_i w^(-3/2), rinv2 = 1/w.
-template <int K>
-__device__ __forceinline__ void chain_pair(const double (&r)[3], const double (&v)[3], const double (&a)[3],
-                                           const double (&j)[3], double mj3, double nmi3, double rinv2,
-                                           double (&acc_i)[K + 1][3], double (&acc_j)[K + 1][3])
+// mj3 = G m_j w^(-3/2), nmi3 = -G m_i w^(-3/2), rinv2 = 1/w; T is double
+// (FP64 chain) or float (mixed chain, from the FP64 differences' casts).
+template <int K, typename T>
+__device__ __forceinline__ void chain_pair(const T (&r)[3], const T (&v)[3], const T (&a)[3], const T (&j)[3],
+                                           T mj3, T nmi3, T rinv2, T (&acc_i)[K + 1][3], T (&acc_j)[K + 1][3])
 {
     static_assert(K >= 1 && K <= 3, "chain supports 1..3 derivatives");
-    const double rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
-    const double alpha = rv * rinv2;
-    double vv = 0.0, ra = 0.0, va = 0.0, rj = 0.0;
+    const T rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
+    const T alpha = rv * rinv2;
+    T vv = T(0), ra = T(0), va = T(0), rj = T(0);
     if constexpr (K >= 2) {
         vv = fma_t(v[2], v[2], fma_t(v[1], v[1], v[0] * v[0]));
         ra = fma_t(r[2], a[2], fma_t(r[1], a[1], r[0] * a[0]));
@@ -123,8 +123,8 @@ __device__ __forceinline__ void chain_pair(const double (&r)[3], const double (&
         va = fma_t(v[2], a[2], fma_t(v[1], a[1], v[0] * a[0]));
         rj = fma_t(r[2], j[2], fma_t(r[1], j[1], r[0] * j[0]));
     }
-    const double n1 = -3.0 * alpha;
-    double J[3];
+    const T n1 = T(-3) * alpha;
+    T J[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         acc_i[0][c] = fma_t(mj3, r[c], acc_i[0][c]);
@@ -134,11 +134,11 @@ __device__ __forceinline__ void chain_pair(const double (&r)[3], const double (&
         acc_j[1][c] = fma_t(nmi3, J[c], acc_j[1][c]);
     }
     if constexpr (K >= 2) {
-        const double alpha2 = alpha * alpha;
-        const double beta = fma_t(vv + ra, rinv2, alpha2);
-        const double n2 = 2.0 * n1;
-        const double n3 = -3.0 * beta;
-        double S[3];
+        const T alpha2 = alpha * alpha;
+        const T beta = fma_t(vv + ra, rinv2, alpha2);
+        const T n2 = T(2) * n1;
+        const T n3 = T(-3) * beta;
+        T S[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             S[c] = fma_t(n3, r[c], fma_t(n2, J[c], a[c]));
@@ -146,16 +146,72 @@ __device__ __forceinline__ void chain_pair(const double (&r)[3], const double (&
             acc_j[2][c] = fma_t(nmi3, S[c], acc_j[2][c]);
         }
         if constexpr (K >= 3) {
-            const double gamma = fma_t(fma_t(3.0, va, rj), rinv2, alpha * fma_t(-4.0, alpha2, -1.0 * n3));
-            const double n4 = 3.0 * n1;
-            const double n5 = 3.0 * n3;
-            const double n6 = -3.0 * gamma;
+            const T gamma = fma_t(fma_t(T(3), va, rj), rinv2, alpha * fma_t(T(-4), alpha2, T(-1) * n3));
+            const T n4 = T(3) * n1;
+            const T n5 = T(3) * n3;
+            const T n6 = T(-3) * gamma;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double C = fma_t(n6, r[c], fma_t(n5, J[c], fma_t(n4, S[c], j[c])));
+                const T C = fma_t(n6, r[c], fma_t(n5, J[c], fma_t(n4, S[c], j[c])));
                 acc_i[3][c] = fma_t(mj3, C, acc_i[3][c]);
                 acc_j[3][c] = fma_t(nmi3, C, acc_j[3][c]);
             }
+        }
+    }
+}
+
+// The split chain taken once for both bodies: orders 0 and 1 in FP64 with
+// exactly chain_pair<K, double>'s operations (so the same bits), orders 2..K
+// in FP32 as chain_split forms them, each body with its own mass factor.
+template <int K>
+__device__ __forceinline__ void chain_split_pair(const double (&r)[3], const double (&v)[3], const float (&af)[3],
+                                                 const float (&jf)[3], double mj3, double nmi3, double rinv2,
+                                                 double (&acc_i)[K + 1][3], double (&acc_j)[K + 1][3],
+                                                 float (&accf_i)[K + 1][3], float (&accf_j)[K + 1][3])
+{
+    static_assert(K >= 2 && K <= 3, "the split chain has FP32 orders 2..K");
+    const double rv = fma_t(r[2], v[2], fma_t(r[1], v[1], r[0] * v[0]));
+    const double alpha = rv * rinv2;
+    const double n1 = -3.0 * alpha;
+    float Jf[3], rf[3], vf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc_i[0][c] = fma_t(mj3, r[c], acc_i[0][c]);
+        acc_j[0][c] = fma_t(nmi3, r[c], acc_j[0][c]);
+        const double J = fma_t(n1, r[c], v[c]);
+        acc_i[1][c] = fma_t(mj3, J, acc_i[1][c]);
+        acc_j[1][c] = fma_t(nmi3, J, acc_j[1][c]);
+        Jf[c] = (float)J;
+        rf[c] = (float)r[c];
+        vf[c] = (float)v[c];
+    }
+    const float alf = (float)alpha, r2f = (float)rinv2, mfi = (float)mj3, mfj = (float)nmi3;
+    const float vv = fma_t(vf[2], vf[2], fma_t(vf[1], vf[1], vf[0] * vf[0]));
+    const float ra = fma_t(rf[2], af[2], fma_t(rf[1], af[1], rf[0] * af[0]));
+    const float alpha2 = alf * alf;
+    const float beta = fma_t(vv + ra, r2f, alpha2);
+    const float n1f = -3.0f * alf;
+    const float n2 = 2.0f * n1f;
+    const float n3 = -3.0f * beta;
+    float S[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        S[c] = fma_t(n3, rf[c], fma_t(n2, Jf[c], af[c]));
+        accf_i[2][c] = fma_t(mfi, S[c], accf_i[2][c]);
+        accf_j[2][c] = fma_t(mfj, S[c], accf_j[2][c]);
+    }
+    if constexpr (K >= 3) {
+        const float va = fma_t(vf[2], af[2], fma_t(vf[1], af[1], vf[0] * af[0]));
+        const float rj = fma_t(rf[2], jf[2], fma_t(rf[1], jf[1], rf[0] * jf[0]));
+        const float gamma = fma_t(fma_t(3.0f, va, rj), r2f, alf * fma_t(-4.0f, alpha2, -1.0f * n3));
+        const float n4 = 3.0f * n1f;
+        const float n5 = 3.0f * n3;
+        const float n6 = -3.0f * gamma;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float C = fma_t(n6, rf[c], fma_t(n5, Jf[c], fma_t(n4, S[c], jf[c])));
+            accf_i[3][c] = fma_t(mfi, C, accf_i[3][c]);
+            accf_j[3][c] = fma_t(mfj, C, accf_j[3][c]);
         }
     }
 }

@@ -205,8 +205,8 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
                                  : jsource == 1 ? hermite::JSource::Scalar
                                                 : hermite::JSource::Lds;
     hermite::LaunchShape sh{ipt, waves, src};
-    if (src == hermite::JSource::Pairs && (chain != Chain::Fp64 || !pairs_fit(ctx, s->n)))
-        return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation needs FP64 and n <= 32768");
+    if (src == hermite::JSource::Pairs && (chain == Chain::Generic || !pairs_fit(ctx, s->n)))
+        return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation needs n <= 32768");
     if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
     HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
     return HERMITE_OK;
@@ -350,10 +350,10 @@ hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_
                     "hermite: 3 or 4 i-particles per lane need the scalar j-source and 4-wave workgroups");
     if (j_split < 0 || j_split > 64) return fail(ctx, HERMITE_E_ARG, "hermite: j_split must be in 0..64");
     if (j_source < 0 || j_source > 2) return fail(ctx, HERMITE_E_ARG, "hermite: j_source must be 0, 1 or 2");
-    if (j_source == 2 && (i_per_thread != 1 || wg_waves != 4 || ctx->prm.precision != HERMITE_FP64))
+    if (j_source == 2 && (i_per_thread != 1 || wg_waves != 4))
         return fail(ctx, HERMITE_E_ARG,
-                    "hermite: the every-pair-once evaluation (j_source 2) is FP64 with one i-particle per lane "
-                    "and 4-wave workgroups");
+                    "hermite: the every-pair-once evaluation (j_source 2) takes one i-particle per lane and "
+                    "4-wave workgroups");
     if (wg_waves != 4 && wg_waves != 16) return fail(ctx, HERMITE_E_ARG, "hermite: wg_waves must be 4 or 16");
     if (wg_waves == 16 && (i_per_thread != 1 || j_source != 1))
         return fail(ctx, HERMITE_E_ARG,
@@ -595,8 +595,8 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
         for (const Cand &cd : shapes) {
             std::vector<int> cands;
             if (cd.src == 2) {
-                // every pair once: FP64, when its partial sums fit; no j-split
-                if (ctx->prm.precision != HERMITE_FP64 || !pairs_fit(ctx, s->n)) continue;
+                // every pair once, when its partial sums fit; no j-split
+                if (!pairs_fit(ctx, s->n)) continue;
                 cands = {0};
             } else {
                 const hermite::LaunchShape sh{cd.ipt, cd.waves,

@@ -1,7 +1,9 @@
-// O(N^2) evaluation with every pair taken once (FP64): the pair's chain
-// serves both bodies (Newton's third law extended to the derivatives: the
-// vectors r, J', S', C' change sign under i <-> j, the scalars alpha, beta,
-// gamma do not), so the chain runs N (N - 1) / 2 times instead of N (N - 1).
+// O(N^2) evaluation with every pair taken once: the pair's chain serves
+// both bodies (Newton's third law extended to the derivatives: the vectors
+// r, J', S', C' change sign under i <-> j, the scalars alpha, beta, gamma do
+// not), so the chain runs N (N - 1) / 2 times instead of N (N - 1).  Chains:
+// FP64; mixed (FP64 differences, then the FP32 chain); split (orders 0 and 1
+// as in FP64, bitwise, orders 2 and 3 in FP32).
 //
 // Work items are pairs (I, J), I <= J, of super-blocks of 256 bodies; one
 // workgroup of 4 wave64 per item.  Wave w keeps the 64 bodies of i-block w of
@@ -16,7 +18,9 @@
 // the phases.  On the diagonal item (I = J) each unordered pair of blocks is
 // visited once (phases 0, 1, and 2 for waves 0 and 1 only), and inside a
 // block each unordered pair of bodies once (steps 1..32, step 32 on lanes
-// 0..31 only).
+// 0..31 only).  FP32 sums (mixed, and split orders 2 and 3) cover at most 32
+// steps: then the i-side folds into its FP64 sums and the j-side into the LDS
+// sums (the same 32-term bound as the other kernels' FP32 partial sums).
 //
 // Outputs per item: the i-side sums of super-block I and the j-side sums of
 // super-block J (partial sums in HBM); a second kernel adds, for every body,
@@ -48,6 +52,15 @@ __device__ __forceinline__ double lane_down(double x)
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ float lane_down(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xF, 0xF, false));
+}
+
+// First derivative order a chain sums in FP32 (K + 1: none).
+template <Chain CH, int K>
+constexpr int f32_from() { return CH == Chain::Mixed ? 0 : CH == Chain::Split ? 2 : K + 1; }
+
 // Item k -> (I, J): the NS (NS - 1) / 2 off-diagonal items first, row by
 // row, then the NS diagonal ones (they carry ~5/8 of an item's work and end
 // the launch).
@@ -74,14 +87,17 @@ __device__ __forceinline__ int64_t item_index(int I, int J, int ns)
     return (int64_t)I * (ns - 1) - (int64_t)I * (I - 1) / 2 + (J - I - 1);
 }
 
-template <int K, bool QM>
+template <int K, Chain CH, bool QM>
 __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
                                                           double G, double eps2, int ns, double *__restrict__ part,
                                                           double *__restrict__ qpart)
 {
     constexpr int NV = (K + 1) * 3;
-    __shared__ double sj[NV + 1][kPS];   // j super-block: G m, then x, v, (a, adot) components
-    __shared__ double jsum[NV][kPS];     // j-side sums of the item
+    constexpr int F = f32_from<CH, K>();   // orders F..K are summed in FP32 first
+    constexpr int kFoldSteps = 32;         // sweep steps per FP32 partial sum
+    __shared__ double sj[NV + 1][kPS];     // j super-block: G m, then x, v, (a, adot) components
+    __shared__ double jsum[NV][kPS];       // j-side sums of the item
+    __shared__ float sjm[CH == Chain::Mixed ? kPS : 1];   // FP32 G m (mixed chain)
     __shared__ double wq[kPW];
     const int tid = threadIdx.x;
     const int w = tid / kPL, l = tid % kPL;
@@ -91,7 +107,9 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
 
     const int64_t jg = (int64_t)J * kPS + tid;
     const bool jok = jg < n;
-    sj[0][tid] = jok ? G * mass[jg] : 0.0;
+    const double gmj_own = jok ? G * mass[jg] : 0.0;
+    sj[0][tid] = gmj_own;
+    if constexpr (CH == Chain::Mixed) sjm[tid] = (float)gmj_own;
 #pragma unroll
     for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -102,13 +120,16 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
     const int64_t ig = (int64_t)I * kPS + tid;
     const bool iok = ig < n;
     const double gmi = iok ? G * mass[ig] : 0.0;
+    const float gmif = (float)gmi;
     double xi[K + 1][3], acc_i[K + 1][3];
+    float accf_i[K + 1][3];
 #pragma unroll
     for (int k = 0; k <= K; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             xi[k][c] = iok ? path.p[k][c * n + ig] : 0.0;
             acc_i[k][c] = 0.0;
+            accf_i[k][c] = 0.0f;
         }
     double qmax = 0.0;
     // j-bodies of super-block J that exist
@@ -121,41 +142,102 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
         const bool same = diag && s == 0;                 // the wave's own block
         if (!(diag && s == 2 && w >= 2)) {                // wave-uniform
             double acc_j[K + 1][3];
+            float accf_j[K + 1][3];
 #pragma unroll
             for (int k = 0; k <= K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) acc_j[k][c] = 0.0;
-            const int t0 = same ? 1 : 0, t1 = same ? kPL / 2 : kPL - 1;
-            for (int t = t0; t <= t1; ++t) {
-                const int js = v * kPL + ((l + t) & (kPL - 1));
-                const bool ok = iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2);
-                double r[3], vv[3], a[3], jk[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    r[c] = sj[1 + c][js] - xi[0][c];
-                    vv[c] = sj[4 + c][js] - xi[1][c];
-                    if constexpr (K >= 2) a[c] = sj[7 + c][js] - xi[2][c]; else a[c] = 0.0;
-                    if constexpr (K >= 3) jk[c] = sj[10 + c][js] - xi[3][c]; else jk[c] = 0.0;
+                    acc_j[k][c] = 0.0;
+                    accf_j[k][c] = 0.0f;
                 }
-                double w2 = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
-                w2 = ok ? w2 : 1.0;
-                const double rinv = rsqrt64(w2);
-                const double rinv2 = rinv * rinv;
-                const double q3 = ok ? rinv * rinv2 : 0.0;
-                const double gmj = sj[0][js];
-                if constexpr (QM) qmax = __builtin_fmax(qmax, (gmi + gmj) * q3);
-                chain_pair<K>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j);
+            const int t0 = same ? 1 : 0, t1 = same ? kPL / 2 : kPL - 1;
+            for (int tc = t0; tc <= t1; tc += kFoldSteps) {
+                const int te = min(t1, tc + kFoldSteps - 1);
+                for (int t = tc; t <= te; ++t) {
+                    const int js = v * kPL + ((l + t) & (kPL - 1));
+                    const bool ok = iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2);
+                    if constexpr (CH == Chain::Mixed) {
+                        float r[3], vv[3], a[3], jk[3];
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                        for (int c = 0; c < 3; ++c) {
+                            r[c] = (float)(sj[1 + c][js] - xi[0][c]);
+                            vv[c] = (float)(sj[4 + c][js] - xi[1][c]);
+                            if constexpr (K >= 2) a[c] = (float)(sj[7 + c][js] - xi[2][c]); else a[c] = 0.0f;
+                            if constexpr (K >= 3) jk[c] = (float)(sj[10 + c][js] - xi[3][c]); else jk[c] = 0.0f;
+                        }
+                        float w2 = __builtin_fmaf(r[0], r[0],
+                                                  __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], (float)eps2)));
+                        w2 = ok ? w2 : 1.0f;
+                        const float rinv = rsqrt32(w2);
+                        const float rinv2 = rinv * rinv;
+                        const float q3 = ok ? rinv * rinv2 : 0.0f;
+                        chain_pair<K, float>(r, vv, a, jk, sjm[js] * q3, -gmif * q3, rinv2, accf_i, accf_j);
+                    } else {
+                        double r[3], vv[3];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc_j[k][c] = lane_down(acc_j[k][c]);
+                        for (int c = 0; c < 3; ++c) {
+                            r[c] = sj[1 + c][js] - xi[0][c];
+                            vv[c] = sj[4 + c][js] - xi[1][c];
+                        }
+                        double w2 =
+                            __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                        w2 = ok ? w2 : 1.0;
+                        const double rinv = rsqrt64(w2);
+                        const double rinv2 = rinv * rinv;
+                        const double q3 = ok ? rinv * rinv2 : 0.0;
+                        const double gmj = sj[0][js];
+                        if constexpr (QM) qmax = __builtin_fmax(qmax, (gmi + gmj) * q3);
+                        if constexpr (CH == Chain::Split) {
+                            float a[3], jk[3];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                a[c] = (float)(sj[7 + c][js] - xi[2][c]);
+                                if constexpr (K >= 3) jk[c] = (float)(sj[10 + c][js] - xi[3][c]); else jk[c] = 0.0f;
+                            }
+                            chain_split_pair<K>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j, accf_i,
+                                                accf_j);
+                        } else {
+                            double a[3], jk[3];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                if constexpr (K >= 2) a[c] = sj[7 + c][js] - xi[2][c]; else a[c] = 0.0;
+                                if constexpr (K >= 3) jk[c] = sj[10 + c][js] - xi[3][c]; else jk[c] = 0.0;
+                            }
+                            chain_pair<K, double>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (k < F) acc_j[k][c] = lane_down(acc_j[k][c]);
+                            else accf_j[k][c] = lane_down(accf_j[k][c]);
+                        }
+                }
+                if constexpr (F <= K) {
+                    // fold the FP32 sums of these steps: the i-side into its FP64
+                    // sums, the j-side (now held by the lane of j-body
+                    // (l + te + 1) mod 64) into the LDS sums of block v
+                    const int jf = v * kPL + ((l + te + 1) & (kPL - 1));
+#pragma unroll
+                    for (int k = F; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            acc_i[k][c] += (double)accf_i[k][c];
+                            accf_i[k][c] = 0.0f;
+                            jsum[3 * k + c][jf] += (double)accf_j[k][c];
+                            accf_j[k][c] = 0.0f;
+                        }
+                }
             }
-            // lane l now holds the sums of j-body (l + t1 + 1) mod 64 of block v
-            const int js_end = v * kPL + ((l + t1 + 1) & (kPL - 1));
+            if constexpr (F > 0) {
+                // lane l now holds the FP64 sums of j-body (l + t1 + 1) mod 64 of block v
+                const int js_end = v * kPL + ((l + t1 + 1) & (kPL - 1));
 #pragma unroll
-            for (int k = 0; k <= K; ++k)
+                for (int k = 0; k < F && k <= K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) jsum[3 * k + c][js_end] += acc_j[k][c];
+                    for (int c = 0; c < 3; ++c) jsum[3 * k + c][js_end] += acc_j[k][c];
+            }
         }
         __syncthreads();
     }
@@ -200,15 +282,15 @@ __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__r
     out[e] = s;
 }
 
-template <int K, bool QM>
+template <int K, Chain CH, bool QM>
 hipError_t launch_k(const ForceArgs &a, hipStream_t st)
 {
     PPath<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     const int ns = (int)((a.n + kPS - 1) / kPS);
     const int64_t items = pairs_items(a.n);
-    hipLaunchKernelGGL((force_pairs_kernel<K, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass, path, a.G,
-                       a.eps2, ns, a.partial, a.qpart);
+    hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass, path,
+                       a.G, a.eps2, ns, a.partial, a.qpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nv = (K + 1) * 3;
@@ -216,6 +298,16 @@ hipError_t launch_k(const ForceArgs &a, hipStream_t st)
     hipLaunchKernelGGL(reduce_pairs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n, nv, ns,
                        (const double *)a.partial, a.out);
     return hipGetLastError();
+}
+
+template <Chain CH, bool QM>
+hipError_t launch_chain(const ForceArgs &a, hipStream_t st)
+{
+    switch (a.K) {
+        case 1: return launch_k<1, CH == Chain::Split ? Chain::Fp64 : CH, QM>(a, st);   // split = FP64 at 4th order
+        case 2: return launch_k<2, CH, QM>(a, st);
+        default: return launch_k<3, CH, QM>(a, st);
+    }
 }
 
 }  // namespace
@@ -228,20 +320,23 @@ int64_t pairs_items(int64_t n)
 
 int64_t pairs_partial_doubles(int64_t n, int K) { return pairs_items(n) * 2 * (K + 1) * 3 * kPS; }
 
-hipError_t launch_force_pairs(const ForceArgs &a, hipStream_t st)
+hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
     if (a.k_first != 0 || a.K < 1 || a.K > 3 || a.n > kPairsMaxN) return hipErrorInvalidValue;
     if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
     const bool qm = a.qpart != nullptr;
     if (qm) {
-        if (pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
+        // the pair rate needs the FP64 1/r: FP64 and split chains only
+        if (chain == Chain::Mixed || pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
         if (a.q_count) *a.q_count = (int)pairs_items(a.n);
     }
-    switch (a.K) {
-        case 1: return qm ? launch_k<1, true>(a, st) : launch_k<1, false>(a, st);
-        case 2: return qm ? launch_k<2, true>(a, st) : launch_k<2, false>(a, st);
-        default: return qm ? launch_k<3, true>(a, st) : launch_k<3, false>(a, st);
+    switch (chain) {
+        case Chain::Fp64: return qm ? launch_chain<Chain::Fp64, true>(a, st) : launch_chain<Chain::Fp64, false>(a, st);
+        case Chain::Split:
+            return qm ? launch_chain<Chain::Split, true>(a, st) : launch_chain<Chain::Split, false>(a, st);
+        case Chain::Mixed: return launch_chain<Chain::Mixed, false>(a, st);
+        default: return hipErrorInvalidValue;
     }
 }
 

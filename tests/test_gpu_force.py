@@ -13,6 +13,7 @@ from parity_util import TOL_FP64, TOL_MIXED, deriv_error, disc_path, random_path
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+PAIRS = (1, 0, 2, 4)   # launch shape of the every-pair-once evaluation (j_source 2)
 
 
 def _say(*a):
@@ -86,43 +87,62 @@ def test_force_derivs_launch_shapes(order, shape, source):
     assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
 
 
-PAIRS = (1, 0, 2, 4)   # every pair once (j_source 2)
+def _pairs_ok(g, o, mag, nat, precision):
+    if precision == "fp64":
+        return deriv_error(g, o, mag).max() <= TOL_FP64
+    if precision == "mixed":
+        return within(deriv_error(g, o, mag, nat), TOL_MIXED)
+    # split: a, adot at the FP64 bar, the FP32 orders at the mixed bars
+    e64 = deriv_error(g[:2], o[:2], mag[:2])
+    ok = e64.max() <= TOL_FP64
+    if len(g) > 2:
+        e32 = deriv_error(g, o, mag, nat)[2:]
+        ok = ok and bool(np.all(e32.max(axis=1) <= np.asarray(TOL_MIXED)[2:len(g)]))
+    return ok
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
 @pytest.mark.parametrize("order", [4, 6, 8])
 @pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 255, 256, 257, 511, 700, 1000, 2050])
-def test_force_derivs_pairs_once(order, n):
+def test_force_derivs_pairs_once(order, n, precision):
     # every pair taken once for both bodies: ragged n over one and several
     # 256-body super-blocks (diagonal and off-diagonal items, partial blocks)
-    _say("force_derivs pairs-once order=%d n=%d" % (order, n))
+    _say("force_derivs pairs-once order=%d n=%d %s" % (order, n, precision))
     p = order // 2 - 1
     w, path = disc_path(n, p)
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, with_mag=True, with_scale=True)
-    g = _eval_gpu(order, w["mass"], path, "fp64", launch=PAIRS)
-    assert deriv_error(g, o, mag).max() <= TOL_FP64
+    g = _eval_gpu(order, w["mass"], path, precision, launch=PAIRS)
+    assert _pairs_ok(g, o, mag, nat, precision)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
 @pytest.mark.parametrize("order", [4, 6, 8])
-def test_force_derivs_pairs_once_softened_and_reproducible(order):
-    _say("force_derivs pairs-once softened order=%d" % order)
+def test_force_derivs_pairs_once_softened_and_reproducible(order, precision):
+    _say("force_derivs pairs-once softened order=%d %s" % (order, precision))
     rng = np.random.default_rng(10 + order)
     p = order // 2 - 1
     n = 1531
     mass, path = random_path(rng, n, p)
     o, mag, nat = ho.pair_derivs(mass, path, K=p, eps2=1e-4, G=0.7, with_mag=True, with_scale=True)
-    g = _eval_gpu(order, mass, path, "fp64", eps2=1e-4, G=0.7, launch=PAIRS)
-    assert deriv_error(g, o, mag).max() <= TOL_FP64
-    assert np.array_equal(g, _eval_gpu(order, mass, path, "fp64", eps2=1e-4, G=0.7, launch=PAIRS))
+    g = _eval_gpu(order, mass, path, precision, eps2=1e-4, G=0.7, launch=PAIRS)
+    assert _pairs_ok(g, o, mag, nat, precision)
+    assert np.array_equal(g, _eval_gpu(order, mass, path, precision, eps2=1e-4, G=0.7, launch=PAIRS))
+
+
+@pytest.mark.parametrize("order", [6, 8])
+def test_pairs_once_split_low_orders_bitwise_fp64(order):
+    # split a and adot take exactly the FP64 pairs kernel's operations
+    _say("pairs-once split vs fp64 bitwise order=%d" % order)
+    p = order // 2 - 1
+    w, path = disc_path(1300, p)
+    gs = _eval_gpu(order, w["mass"], path, "split", launch=PAIRS)
+    gf = _eval_gpu(order, w["mass"], path, "fp64", launch=PAIRS)
+    assert np.array_equal(gs[:2], gf[:2])
 
 
 def test_pairs_once_limits():
     _say("pairs-once limits")
     from paper_2006_02501_amd import HermiteError
-    for prec in ("mixed", "split"):
-        h = Hermite(8, 16, precision=prec, device=DEV)
-        with pytest.raises(HermiteError):
-            h.set_launch(*PAIRS)
-        h.close()
     h = Hermite(8, 16, device=DEV)
     for bad in [(2, 0, 2, 4), (1, 0, 2, 16)]:
         with pytest.raises(HermiteError):
@@ -143,7 +163,7 @@ def test_pairs_once_limits():
 def test_set_launch_validation():
     h = Hermite(8, 16, device=DEV)
     from paper_2006_02501_amd import HermiteError
-    for bad in [(5, 0, 1, 4), (0, 0, 1, 4), (3, 0, 0, 4), (4, 0, 1, 16), (1, 65, 1, 4), (1, 0, 2, 4),
+    for bad in [(5, 0, 1, 4), (0, 0, 1, 4), (3, 0, 0, 4), (4, 0, 1, 16), (1, 65, 1, 4), (1, 0, 3, 4),
                 (1, 0, 1, 8), (2, 0, 1, 16), (1, 0, 0, 16)]:
         with pytest.raises(HermiteError):
             h.set_launch(*bad)
@@ -177,7 +197,7 @@ def test_force_derivs_bitwise_reproducible():
 # Launch shapes (i_per_thread, j_split, j_source, wg_waves) that the
 # benchmark's autotuner picks on the 16k disc and that its traffic profile
 # was taken with.
-BENCH_SHAPES = {"fp64": (2, 4, 0, 4), "mixed": (1, 64, 1, 4), "split": (1, 64, 1, 4)}
+BENCH_SHAPES = {"fp64": (1, 0, 2, 4), "mixed": (1, 64, 1, 4), "split": (1, 64, 1, 4)}
 
 
 
@@ -211,8 +231,9 @@ def test_force_derivs_full_size_sampled(precision):
     tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
     g_def = _eval_gpu(8, w["mass"], path, precision)
     g_bench = _eval_gpu(8, w["mass"], path, precision, launch=BENCH_SHAPES[precision])
+    g_pairs = _eval_gpu(8, w["mass"], path, precision, launch=PAIRS)
     g_tuned, shape = _eval_autotuned(8, w["mass"], path, precision)
-    for name, g in (("default", g_def), ("bench", g_bench), ("autotuned %s" % (shape,), g_tuned)):
+    for name, g in (("default", g_def), ("bench", g_bench), ("pairs", g_pairs), ("autotuned %s" % (shape,), g_tuned)):
         err = deriv_error(g[:, :, il], o, mag, None if precision == "fp64" else nat)
         _say("  %s %s max err per order %s" % (precision, name, err.max(axis=1)))
         assert within(err, tol), (precision, name, err.max(axis=1))
@@ -220,7 +241,7 @@ def test_force_derivs_full_size_sampled(precision):
         # every launch shape sums the same FP64 terms; they differ only in
         # the order of the additions
         scale = np.abs(g_bench).max(axis=(1, 2), keepdims=True)
-        for g in (g_def, g_tuned):
+        for g in (g_def, g_pairs, g_tuned):
             assert (np.abs(g - g_bench) / scale).max() <= 1e-13
 
 

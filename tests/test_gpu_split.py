@@ -16,7 +16,7 @@ from parity_util import TOL_FP64, TOL_MIXED, deriv_error, disc_path, random_path
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
-SHAPES = [(1, 1, 0, 4), (2, 3, 0, 4), (1, 64, 1, 4), (2, 0, 1, 4), (1, 3, 1, 16), (1, 0, 1, 16)]
+SHAPES = [(1, 1, 0, 4), (2, 3, 0, 4), (1, 64, 1, 4), (2, 0, 1, 4), (1, 3, 1, 16), (1, 0, 1, 16), (1, 0, 2, 4)]
 
 
 def _say(*a):
@@ -81,7 +81,7 @@ def test_split_random_softened(order):
     assert _ok(deriv_error(g, o, mag, nat)[2:], TOL_MIXED[2:p + 1])
 
 
-@pytest.mark.parametrize("launch", [None, (1, 64, 1, 4)])
+@pytest.mark.parametrize("launch", [None, (1, 64, 1, 4), (1, 0, 2, 4)])
 def test_split_full_size_sampled(launch):
     # the 16k disc at its full size, 192 sampled i, in the default launch shape
     # and in the one the benchmark times

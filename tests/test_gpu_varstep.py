@@ -143,7 +143,8 @@ def test_symmetric_step_reversible_on_gpu():
     assert abs(d1["t"]) < 1e-15
 
 
-@pytest.mark.parametrize("launch", [(1, 1, 0, 4), (2, 3, 0, 4), (1, 64, 1, 4), (2, 0, 1, 4), (1, 5, 1, 16)])
+@pytest.mark.parametrize("launch", [(1, 1, 0, 4), (2, 3, 0, 4), (1, 64, 1, 4), (2, 0, 1, 4), (1, 5, 1, 16),
+                                    (1, 0, 2, 4)])
 @pytest.mark.parametrize("precision", ["fp64", "split"])
 def test_fused_rate_in_every_launch_shape(launch, precision):
     # FP64 and split evaluations take the pair rate along (one maximum per
