@@ -40,37 +40,37 @@ KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_025
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
+        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 124782214,
+        "fetch_bytes": 124691387,
         "write_bytes": 103809024
     },
     "mixed": {
-        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
+        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
         "launch": {
             "i_per_thread": 1,
-            "j_split": 64,
-            "j_source": "scalar",
+            "j_split": 0,
+            "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 137600524,
-        "write_bytes": 104333312
+        "fetch_bytes": 124496576,
+        "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "c352b80f1139a718857382174de3ad90bcde07fb4b56a2dd7c43749a06090617",
+        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
         "launch": {
             "i_per_thread": 1,
-            "j_split": 64,
-            "j_source": "scalar",
+            "j_split": 0,
+            "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 137599714,
-        "write_bytes": 104333312
+        "fetch_bytes": 124671933,
+        "write_bytes": 103809024
     }
 }
 # j_source codes of hermite_set_launch: LDS tiles, scalar stream, every pair once

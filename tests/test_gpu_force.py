@@ -171,16 +171,36 @@ def test_set_launch_validation():
     h.close()
 
 
-def test_force_derivs_single_particle_and_empty():
-    _say("force_derivs n=1 and n=0")
-    g = _eval_gpu(8, np.array([1.0]), [np.ones((3, 1))] * 4)
-    assert np.array_equal(g, np.zeros((4, 3, 1)))
+@pytest.mark.parametrize("launch", [None, PAIRS])
+def test_force_derivs_single_particle_and_empty(launch):
+    _say("force_derivs n=1 and n=0", launch)
+    for prec in ("fp64", "mixed", "split"):
+        g = _eval_gpu(8, np.array([1.0]), [np.ones((3, 1))] * 4, prec, launch=launch)
+        assert np.array_equal(g, np.zeros((4, 3, 1)))
     h = Hermite(8, 0, device=DEV)
+    if launch is not None:
+        h.set_launch(*launch)
     st = h.state(np.zeros(0), np.zeros((3, 0)), np.zeros((3, 0)))
     h.force_derivs(st)
     h.init(st)
     h.step(st, 0.1, 2)
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
+def test_force_derivs_pairs_once_coincident_softened(precision):
+    # bodies at the same place with softening: the pair terms are finite
+    # (r = 0 gives zero force, the softened derivatives stay finite)
+    _say("pairs-once coincident softened", precision)
+    n = 300
+    rng = np.random.default_rng(8)
+    mass, path = random_path(rng, n, 3)
+    for k in range(4):
+        path[k][:, 100:110] = path[k][:, 100:101]      # ten bodies at one point with one path
+    o, mag, nat = ho.pair_derivs(mass, path, K=3, eps2=1e-6, with_mag=True, with_scale=True)
+    g = _eval_gpu(8, mass, path, precision, eps2=1e-6, launch=PAIRS)
+    assert np.all(np.isfinite(g))
+    assert _pairs_ok(g, o, mag, nat, precision)
 
 
 def test_force_derivs_bitwise_reproducible():
@@ -194,11 +214,12 @@ def test_force_derivs_bitwise_reproducible():
     assert np.array_equal(c, d)
 
 
-# Launch shapes (i_per_thread, j_split, j_source, wg_waves) that the
-# benchmark's autotuner picks on the 16k disc and that its traffic profile
-# was taken with.
-BENCH_SHAPES = {"fp64": (1, 0, 2, 4), "mixed": (1, 64, 1, 4), "split": (1, 64, 1, 4)}
-
+# Launch shapes (i_per_thread, j_split, j_source, wg_waves) checked at the
+# full 16k size: every pair once (what the benchmark's autotuner picks on
+# this disc for all three chains, and what its traffic profile was taken
+# with), the scalar stream with 64 splits and the LDS tiles with 4 splits
+# (the earlier picks).
+FULL_SIZE_SHAPES = [PAIRS, (1, 64, 1, 4), (2, 4, 0, 4)]
 
 
 def _eval_autotuned(order, mass, path, precision):
@@ -217,10 +238,10 @@ def _eval_autotuned(order, mass, path, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_force_derivs_full_size_sampled(precision):
-    # Disc of 16384 bodies (8th order): the default launch, the launch the
-    # benchmark times, and whatever the autotuner picks on this device; 512
-    # sampled i-particles checked against the oracle, and (FP64) the three
-    # runs against each other.
+    # Disc of 16384 bodies (8th order): the default launch, the shapes above
+    # (the first is the one the benchmark times) and whatever the autotuner
+    # picks on this device; 512 sampled i-particles checked against the
+    # oracle, and (FP64) the runs against each other.
     _say("force_derivs N=16384 sampled", precision)
     n = 16384
     w, path = disc_path(n, 3)
@@ -229,20 +250,22 @@ def test_force_derivs_full_size_sampled(precision):
     il[0] = 0                     # the central body
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
     tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
-    g_def = _eval_gpu(8, w["mass"], path, precision)
-    g_bench = _eval_gpu(8, w["mass"], path, precision, launch=BENCH_SHAPES[precision])
-    g_pairs = _eval_gpu(8, w["mass"], path, precision, launch=PAIRS)
+    runs = [("default", _eval_gpu(8, w["mass"], path, precision))]
+    for shape in FULL_SIZE_SHAPES:
+        runs.append((str(shape), _eval_gpu(8, w["mass"], path, precision, launch=shape)))
     g_tuned, shape = _eval_autotuned(8, w["mass"], path, precision)
-    for name, g in (("default", g_def), ("bench", g_bench), ("pairs", g_pairs), ("autotuned %s" % (shape,), g_tuned)):
+    runs.append(("autotuned %s" % (shape,), g_tuned))
+    for name, g in runs:
         err = deriv_error(g[:, :, il], o, mag, None if precision == "fp64" else nat)
         _say("  %s %s max err per order %s" % (precision, name, err.max(axis=1)))
         assert within(err, tol), (precision, name, err.max(axis=1))
     if precision == "fp64":
         # every launch shape sums the same FP64 terms; they differ only in
         # the order of the additions
-        scale = np.abs(g_bench).max(axis=(1, 2), keepdims=True)
-        for g in (g_def, g_pairs, g_tuned):
-            assert (np.abs(g - g_bench) / scale).max() <= 1e-13
+        ref = runs[1][1]
+        scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+        for _, g in runs:
+            assert (np.abs(g - ref) / scale).max() <= 1e-13
 
 
 @pytest.mark.parametrize("order", [4, 6, 8])
