@@ -10,6 +10,7 @@ import torch
 from oracle import hermite_oracle as ho
 from paper_2006_02501_amd import Hermite
 from parity_util import TOL_FP64, TOL_MIXED, deriv_error, disc_path, random_path, within
+from workloads import disc16k
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -138,6 +139,31 @@ def test_pairs_once_split_low_orders_bitwise_fp64(order):
     gs = _eval_gpu(order, w["mass"], path, "split", launch=PAIRS)
     gf = _eval_gpu(order, w["mass"], path, "fp64", launch=PAIRS)
     assert np.array_equal(gs[:2], gf[:2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_derivs_pairs_once_largest(precision):
+    # the largest n the every-pair-once path takes (8256 super-block pairs,
+    # 406 MB of partials at 8th order), 128 sampled i against the oracle; the
+    # path's a and adot are the central body's Kepler field
+    _say("pairs-once n=32768", precision)
+    n = 32768
+    w = disc16k(n)
+    x, v = w["x"], w["v"]
+    r2 = np.sum(x * x, axis=0)
+    rv = np.sum(x * v, axis=0)
+    path = [x, v, -x * r2 ** -1.5, -v * r2 ** -1.5 + 3.0 * x * rv * r2 ** -2.5]
+    path[2][:, 0] = 0.0
+    path[3][:, 0] = 0.0
+    rng = np.random.default_rng(12)
+    il = np.sort(rng.choice(n, 128, replace=False))
+    il[0], il[-1] = 0, n - 1
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
+    g = _eval_gpu(8, w["mass"], path, precision, launch=PAIRS)[:, :, il]
+    if precision == "fp64":
+        assert deriv_error(g, o, mag).max() <= TOL_FP64
+    else:
+        assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
 
 
 def test_pairs_once_limits():
