@@ -8,13 +8,15 @@
 // correction after the evaluation at the iterate x_k uses
 // s (H(x0) + H(x_k)) / 2, with s = +1 or -1 the direction of integration.
 //
-// q is a max over N^2 pairs: ~20 FP64 VALU operations per pair (difference,
-// softened distance, refined reciprocal square root, its cube, the mass sum,
-// the max), against ~90 per pair of the 8th-order evaluation.  Workgroups
-// cover (256 i-particles) x (a j-range) and write one maximum each; a
-// single-workgroup kernel folds them and forms H and dt.  A maximum does not
-// depend on the order it is taken in, so the result is the same for every
-// launch shape.
+// q is a max over the N (N - 1) / 2 unordered pairs (the rate is symmetric in
+// i and j, and so is the way it is rounded here): ~20 FP64 VALU operations
+// per pair (difference, softened distance, refined reciprocal square root,
+// its cube, the mass sum, the max), against ~90 per pair of the 8th-order
+// evaluation.  Workgroups cover (256 i-particles) x (a j-range) and take the
+// pairs with j > i; each writes one maximum (0 when it holds no such pair),
+// and a single-workgroup kernel folds them and forms H and dt.  A maximum
+// does not depend on the order it is taken in, so the result is the same for
+// every launch shape.
 #include "kernels.h"
 #include "pair_chain.h"
 
@@ -50,29 +52,32 @@ __device__ __forceinline__ double block_qmax(double q)
 }
 
 // qpart[blockIdx.y * gridDim.x + blockIdx.x] = max of the rate over
-// i in this workgroup's 256 and j in [blockIdx.y * j_chunk, +j_chunk), j != i.
+// i in this workgroup's 256 and j in [blockIdx.y * j_chunk, +j_chunk), j > i.
 // The j loop index is uniform, so the j-particle loads go through the scalar
 // unit; each lane keeps its own i.
 __global__ __launch_bounds__(kQBlock) void qmax_kernel(int64_t n, const double *__restrict__ mass,
                                                        const double *__restrict__ x, double G, double eps2,
                                                        int64_t j_chunk, double *__restrict__ qpart)
 {
-    const int64_t i = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+    const int64_t ib0 = (int64_t)blockIdx.x * kQBlock;
+    const int64_t i = ib0 + threadIdx.x;
     const bool live = i < n;
     const int64_t ic = live ? i : n - 1;
     const double xi = x[ic], yi = x[n + ic], zi = x[2 * n + ic];
-    const double gmi = G * mass[ic];
-    const int64_t j0 = (int64_t)blockIdx.y * j_chunk;
-    const int64_t j1 = j0 + j_chunk < n ? j0 + j_chunk : n;
+    const double mi = mass[ic];
+    // pairs with j > i only: no j at or below the block's first i
+    const int64_t j0 = max((int64_t)blockIdx.y * j_chunk, ib0 + 1);
+    const int64_t j1 = min((int64_t)blockIdx.y * j_chunk + j_chunk, n);
     double best = 0.0;
 #pragma unroll 4
     for (int64_t j = j0; j < j1; ++j) {
         const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
         const double w = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         const double y = rsqrt64(w);
-        // self pair: a zero mass factor (0 or, unsoftened, 0 * inf = NaN; both
-        // leave the max as it is)
-        const double gm = (j == i) ? 0.0 : __builtin_fma(G, mass[j], gmi);
+        // j <= i (the pair is taken from its other end, or the self pair): a
+        // zero mass factor (0 or, unsoftened, 0 * inf = NaN; both leave the
+        // max as it is)
+        const double gm = (j <= i) ? 0.0 : G * (mass[j] + mi);
         best = qcombine(gm * (y * y * y), best);
     }
     best = block_qmax(live ? best : 0.0);
