@@ -58,8 +58,8 @@ int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 // Every-pair-once evaluation (FP64, mixed or split chain, K = 1..3,
 // k_first = 0): work items are pairs of 256-body super-blocks, each writing
 // 2 * (K+1) * 3 * 256 partial sums into a.partial, which a fixed-order
-// reduction adds into a.out.  With a.qpart (FP64 and split chains), one
-// pair-rate maximum per item (a.q_count = the item count).
+// reduction adds into a.out.  With a.qpart, one pair-rate maximum per item
+// (a.q_count = the item count), from FP64 differences in every chain.
 constexpr int64_t kPairsMaxN = 32768;
 int64_t pairs_items(int64_t n);
 int64_t pairs_partial_doubles(int64_t n, int K);

@@ -497,9 +497,11 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
             "step criterion launch");
     HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, dtp, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
             "predict launch");
-    // FP64 and split evaluations take the pair rate along; the mixed one has
-    // only an FP32 1/r, so its criterion is a separate FP64 pass
-    const bool fused = ctx->prm.precision != HERMITE_MIXED;
+    // FP64 and split evaluations take the pair rate along, and so does the
+    // mixed every-pair-once evaluation (from its FP64 differences); the other
+    // mixed kernels have only an FP32 1/r, so their criterion is a separate
+    // FP64 pass
+    const bool fused = ctx->prm.precision != HERMITE_MIXED || ctx->jsource == 2;
     for (int it = 0; it < n_iter; ++it) {
         // evaluation, H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
         if (fused) {

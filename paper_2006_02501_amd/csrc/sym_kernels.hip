@@ -158,9 +158,11 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
                     const bool ok = iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2);
                     if constexpr (CH == Chain::Mixed) {
                         float r[3], vv[3], a[3], jk[3];
+                        double r64[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            r[c] = (float)(sj[1 + c][js] - xi[0][c]);
+                            r64[c] = sj[1 + c][js] - xi[0][c];
+                            r[c] = (float)r64[c];
                             vv[c] = (float)(sj[4 + c][js] - xi[1][c]);
                             if constexpr (K >= 2) a[c] = (float)(sj[7 + c][js] - xi[2][c]); else a[c] = 0.0f;
                             if constexpr (K >= 3) jk[c] = (float)(sj[10 + c][js] - xi[3][c]); else jk[c] = 0.0f;
@@ -171,6 +173,14 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
                         const float rinv = rsqrt32(w2);
                         const float rinv2 = rinv * rinv;
                         const float q3 = ok ? rinv * rinv2 : 0.0f;
+                        if constexpr (QM) {
+                            // the step criterion's rate, from the FP64 differences
+                            double w64 = __builtin_fma(r64[0], r64[0],
+                                                       __builtin_fma(r64[1], r64[1], __builtin_fma(r64[2], r64[2], eps2)));
+                            w64 = ok ? w64 : 1.0;
+                            const double y = rsqrt64(w64);
+                            qmax = __builtin_fmax(qmax, ok ? (gmi + sj[0][js]) * (y * y * y) : 0.0);
+                        }
                         chain_pair<K, float>(r, vv, a, jk, sjm[js] * q3, -gmif * q3, rinv2, accf_i, accf_j);
                     } else {
                         double r[3], vv[3];
@@ -327,15 +337,15 @@ hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st)
     if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
     const bool qm = a.qpart != nullptr;
     if (qm) {
-        // the pair rate needs the FP64 1/r: FP64 and split chains only
-        if (chain == Chain::Mixed || pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
+        if (pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
         if (a.q_count) *a.q_count = (int)pairs_items(a.n);
     }
     switch (chain) {
         case Chain::Fp64: return qm ? launch_chain<Chain::Fp64, true>(a, st) : launch_chain<Chain::Fp64, false>(a, st);
         case Chain::Split:
             return qm ? launch_chain<Chain::Split, true>(a, st) : launch_chain<Chain::Split, false>(a, st);
-        case Chain::Mixed: return launch_chain<Chain::Mixed, false>(a, st);
+        case Chain::Mixed:
+            return qm ? launch_chain<Chain::Mixed, true>(a, st) : launch_chain<Chain::Mixed, false>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

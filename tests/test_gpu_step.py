@@ -85,12 +85,14 @@ def test_correct_parity(order, corrector):
     h.close()
 
 
-def _run_pair(order, w, dt, n_iter, steps, corrector="modified", eps2=0.0, precision="fp64"):
+def _run_pair(order, w, dt, n_iter, steps, corrector="modified", eps2=0.0, precision="fp64", launch=None):
     p = order // 2 - 1
     st_o = ho.State(w["mass"], w["x"], w["v"], p)
     ho.init_derivs(st_o, eps2=eps2)
     n = len(w["mass"])
     h = Hermite(order, n, precision=precision, corrector=corrector, eps2=eps2, device=DEV)
+    if launch is not None:
+        h.set_launch(*launch)
     st = h.state(w["mass"], w["x"], w["v"])
     h.init(st)
     for _ in range(steps):
@@ -121,27 +123,30 @@ def test_step_parity_ring64():
     assert rel_max(g["x"], o.x) <= 1e-10 and rel_max(g["v"], o.v) <= 1e-10
 
 
+@pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
 @pytest.mark.parametrize("order", [6, 8])
-def test_step_parity_disc(order):
-    _say("step disc order=%d" % order)
+def test_step_parity_disc(order, launch):
+    # the default launch and every pair once
+    _say("step disc order=%d launch=%s" % (order, launch))
     w, _ = disc_path(700, 1)
     dt = 2 * np.pi / 2000
-    o, g = _run_pair(order, w, dt, 3, 1)
+    o, g = _run_pair(order, w, dt, 3, 1, launch=launch)
     assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
-    o, g = _run_pair(order, w, dt, 3, 10)
+    o, g = _run_pair(order, w, dt, 3, 10, launch=launch)
     assert rel_max(g["x"], o.x) <= 1e-11 and rel_max(g["v"], o.v) <= 1e-11
     for k in range(order // 2):
         assert rel_max(g["derivs"][k], o.derivs[k]) <= 1e-9, k
 
 
-def test_mixed_step_close_to_fp64():
+@pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
+def test_mixed_step_close_to_fp64(launch):
     # A relative force error delta (1e-6 bar) on |a| <= 100 (r >= 0.1) over
     # T = 5 dt moves v by <= delta |a| T and x by <= delta |a| T^2 / 2:
     # 1.6e-6 / 3 (max |v| ~ 3) and 1.2e-8 (max |x| ~ 1).
-    _say("mixed step vs fp64")
+    _say("mixed step vs fp64 launch=%s" % (launch,))
     w, _ = disc_path(700, 1)
     dt = 2 * np.pi / 2000
-    o, g = _run_pair(8, w, dt, 3, 5, precision="mixed")
+    o, g = _run_pair(8, w, dt, 3, 5, precision="mixed", launch=launch)
     assert rel_max(g["x"], o.x) <= 1.2e-8 and rel_max(g["v"], o.v) <= 5e-7
 
 

@@ -79,12 +79,14 @@ def test_criterion_full_size_planted_binary(where):
     assert abs(g / expect - 1.0) <= TOL_H, (g, expect)
 
 
-def _run_pair(order, w, eta, n_iter, steps, eps2=0.0, precision="fp64", direction=1.0):
+def _run_pair(order, w, eta, n_iter, steps, eps2=0.0, precision="fp64", direction=1.0, launch=None):
     p = order // 2 - 1
     o = ho.State(w["mass"], w["x"], w["v"], p)
     ho.init_derivs(o, eps2=eps2)
     n = len(w["mass"])
     h = Hermite(order, n, precision=precision, eps2=eps2, device=DEV)
+    if launch is not None:
+        h.set_launch(*launch)
     st = h.state(w["mass"], w["x"], w["v"])
     h.init(st)
     dts = []
@@ -190,7 +192,8 @@ def test_fused_rate_pairs_once(nb):
     assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
 
 
-def test_mixed_symmetric_step_within_force_bound():
+@pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
+def test_mixed_symmetric_step_within_force_bound(launch):
     # The mixed evaluation's relative force error delta (<= 1e-6, the bar of
     # the mixed evaluation on a) moves each iterate's x by <= delta a dt^2 / 2
     # and v by <= delta a dt; the step's length follows H ~ r^(3/2) of the
@@ -199,10 +202,12 @@ def test_mixed_symmetric_step_within_force_bound():
     # |t_gpu - t_oracle|, which moves x by v_max |dt| and v by a_max |dt|.
     # (a_max = G M / r_min^2 with r_min the smallest distance to the central
     # mass; v_max = (2 G M / r_min)^(1/2).)  All bounds carry a factor 2.
-    _say("mixed symmetric step disc100")
+    # The default launch takes the criterion from a separate FP64 pass, every
+    # pair once from the evaluation's FP64 differences.
+    _say("mixed symmetric step disc100 launch=%s" % (launch,))
     w = disc100()
     steps = 5
-    o, g, dts = _run_pair(8, w, 0.08, 3, steps, eps2=w["eps2"], precision="mixed")
+    o, g, dts = _run_pair(8, w, 0.08, 3, steps, eps2=w["eps2"], precision="mixed", launch=launch)
     delta = TOL_MIXED[0]
     rc = np.sqrt(np.sum((w["x"][:, 1:] - w["x"][:, :1]) ** 2, axis=0))
     r_min = 0.9 * rc.min()
