@@ -40,36 +40,36 @@ KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_025
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
+        "sources_sha256": "0b7a574825d56f334d1bbfe16aea64aedc33e9eda70f0065d2d970cdcfd1af01",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 124691387,
+        "fetch_bytes": 124905150,
         "write_bytes": 103809024
     },
     "mixed": {
-        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
+        "sources_sha256": "0b7a574825d56f334d1bbfe16aea64aedc33e9eda70f0065d2d970cdcfd1af01",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 124496576,
+        "fetch_bytes": 124448691,
         "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "8e48d7376ad8f9e3fc033185e25b9df7282554e98807830541137f98883ffa1c",
+        "sources_sha256": "0b7a574825d56f334d1bbfe16aea64aedc33e9eda70f0065d2d970cdcfd1af01",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 124671933,
+        "fetch_bytes": 124762573,
         "write_bytes": 103809024
     }
 }

@@ -226,10 +226,11 @@ hermite_status check_finite(hermite_ctx *ctx, const double *const *arrays, const
 
 hermite_status alloc_timestep(hermite_ctx *ctx)
 {
-    // the rate pass writes at most ceil(n/256) + 2048 workgroup maxima; an
-    // evaluation with the fused rate at most one per workgroup, i.e. at most
-    // (ceil(n/64)) * 64 splits
-    ctx->qpart_cap = std::max<int64_t>((ctx->n_max + 255) / 256 + 2049, (ctx->n_max + 63) / 64 * 64);
+    // the rate pass writes at most max(ceil(n/256)^2, ceil(n/256) + 4096)
+    // workgroup maxima (at most 4096 + n/256 for n > 65536, else at most n);
+    // an evaluation with the fused rate at most one per workgroup, i.e. at
+    // most (ceil(n/64)) * 64 splits
+    ctx->qpart_cap = std::max<int64_t>((ctx->n_max + 255) / 256 + 4097, (ctx->n_max + 63) / 64 * 64);
     if (hipMalloc((void **)&ctx->qpart, ctx->qpart_cap * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
     if (hipMalloc((void **)&ctx->vs, 4 * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
     if (hipHostMalloc((void **)&ctx->host_vs, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)

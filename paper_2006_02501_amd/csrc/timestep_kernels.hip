@@ -117,8 +117,9 @@ __global__ __launch_bounds__(kQBlock) void timestep_kernel(const double *__restr
 int qmax_partials(int64_t n, int *nsplit_out, int64_t *j_chunk_out)
 {
     const int64_t nib = (n + kQBlock - 1) / kQBlock;
-    // about 2048 workgroups when N allows it, each j-range at least 256 long
-    int64_t ns = (2048 + nib - 1) / nib;
+    // about 4096 workgroups when N allows it (half of them hold no pair with
+    // j > i), each j-range at least 256 long
+    int64_t ns = (4096 + nib - 1) / nib;
     const int64_t max_ns = (n + 255) / 256;
     if (ns > max_ns) ns = max_ns;
     if (ns < 1) ns = 1;
