@@ -518,7 +518,7 @@ def main():
                          "(i_per_thread, j_split, j_source, wg_waves)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the kernel at one GPU's share); "
+        print("bench.py: one GPU only (the evaluation at one GPU's share); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch  # noqa: F401
