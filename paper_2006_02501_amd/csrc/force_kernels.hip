@@ -541,6 +541,7 @@ __global__ void reduce_splits_kernel(int64_t count, int nsplit, const double *__
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     double s = partial[e];
+#pragma unroll 8
     for (int sp = 1; sp < nsplit; ++sp) s += partial[(int64_t)sp * count + e];
     out[e] = s;
 }

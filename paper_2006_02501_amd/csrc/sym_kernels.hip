@@ -286,8 +286,11 @@ __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__r
     const int64_t b = e - (int64_t)comp * n;
     const int kb = (int)(b / kPS), loc = (int)(b % kPS);
     const int64_t stride = (int64_t)2 * nv * kPS;
+    // (unrolled so that several loads are in flight; the additions keep their order)
     double s = 0.0;
+#pragma unroll 8
     for (int J = kb; J < ns; ++J) s += part[item_index(kb, J, ns) * stride + (int64_t)comp * kPS + loc];
+#pragma unroll 8
     for (int I = 0; I <= kb; ++I) s += part[item_index(I, kb, ns) * stride + (int64_t)(nv + comp) * kPS + loc];
     out[e] = s;
 }
