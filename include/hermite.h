@@ -297,10 +297,11 @@ hermite_status hermite_ensemble_run(hermite_ctx *ctx, hermite_state *s, const he
  *                  records and streamed through the scalar unit into SGPRs;
  *                  2: every pair evaluated once for both of its bodies (the
  *                  chain's vectors change sign under i <-> j), with
- *                  i_per_thread 1 and wg_waves 4, j_split ignored; for
- *                  n <= 32768 (hermite_force_derivs returns E_ARG above),
- *                  partial sums in the context's workspace, added in a fixed
- *                  order
+ *                  i_per_thread 1 and wg_waves 4, j_split ignored; partial
+ *                  sums in the context's workspace, added in a fixed order;
+ *                  one launch up to 32768 bodies, beyond that one launch per
+ *                  pair of chunks of up to 16384 bodies (E_ARG from the
+ *                  evaluation if the workspace cannot hold a chunk pair)
  *   wg_waves       4 or 16 wave64 per workgroup; 16 (scalar source and one
  *                  i-particle per lane only): the waves share 64 i-particles
  *                  and split the j-range among themselves, adding their sums

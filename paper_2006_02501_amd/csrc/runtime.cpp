@@ -173,12 +173,19 @@ int64_t partial_capacity(int64_t n_max, int p)
     return cap;
 }
 
-// The every-pair-once evaluation of n bodies fits this context's workspace.
+// The every-pair-once evaluation of n bodies fits this context's workspace:
+// in one launch up to kPairsMaxN bodies, in chunks beyond.
 bool pairs_fit(const hermite_ctx *ctx, int64_t n)
 {
-    return n <= hermite::kPairsMaxN && hermite::pairs_partial_doubles(n, ctx->p) <= ctx->partial_cap &&
-           hermite::pairs_items(n) <= ctx->qpart_cap;
+    if (n <= hermite::kPairsMaxN)
+        return hermite::pairs_partial_doubles(n, ctx->p) <= ctx->partial_cap &&
+               hermite::pairs_items(n) <= ctx->qpart_cap;
+    return hermite::pairs_chunk(ctx->partial_cap, ctx->p) >= hermite::kPairsMinChunk;
 }
+
+// The every-pair-once evaluation of n bodies takes the step criterion's rate
+// along (one launch; the chunked form does not).
+bool pairs_rate(int64_t n) { return n <= hermite::kPairsMaxN; }
 
 hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
                          const double *const *path, double *out, int ipt, int nsplit, int jsource, int waves,
@@ -206,7 +213,7 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
                                                 : hermite::JSource::Lds;
     hermite::LaunchShape sh{ipt, waves, src};
     if (src == hermite::JSource::Pairs && (chain == Chain::Generic || !pairs_fit(ctx, s->n)))
-        return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation needs n <= 32768");
+        return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation does not fit this context's workspace");
     if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
     HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
     return HERMITE_OK;
@@ -499,10 +506,12 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
     HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, dtp, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
             "predict launch");
     // FP64 and split evaluations take the pair rate along, and so does the
-    // mixed every-pair-once evaluation (from its FP64 differences); the other
-    // mixed kernels have only an FP32 1/r, so their criterion is a separate
-    // FP64 pass
-    const bool fused = ctx->prm.precision != HERMITE_MIXED || ctx->jsource == 2;
+    // mixed every-pair-once evaluation (from its FP64 differences) while it is
+    // one launch; the other mixed kernels have only an FP32 1/r and the
+    // chunked every-pair-once form keeps no rate, so their criterion is a
+    // separate FP64 pass
+    const bool pairs = ctx->jsource == 2;
+    const bool fused = pairs ? pairs_rate(s->n) : ctx->prm.precision != HERMITE_MIXED;
     for (int it = 0; it < n_iter; ++it) {
         // evaluation, H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
         if (fused) {

@@ -87,10 +87,18 @@ __device__ __forceinline__ int64_t item_index(int I, int J, int ns)
     return (int64_t)I * (ns - 1) - (int64_t)I * (I - 1) / 2 + (J - I - 1);
 }
 
+// The super-block pairs of one launch: the triangle I <= J of one chunk of
+// nsi super-blocks starting at ci0 (tri), or the whole rectangle of chunk
+// ci0 (nsi super-blocks) against chunk cj0 (nsj super-blocks).
+struct PairsGrid {
+    int ci0, nsi, cj0, nsj;
+    int tri;
+};
+
 template <int K, Chain CH, bool QM>
 __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
-                                                          double G, double eps2, int ns, double *__restrict__ part,
-                                                          double *__restrict__ qpart)
+                                                          double G, double eps2, PairsGrid pg,
+                                                          double *__restrict__ part, double *__restrict__ qpart)
 {
     constexpr int NV = (K + 1) * 3;
     constexpr int F = f32_from<CH, K>();   // orders F..K are summed in FP32 first
@@ -101,9 +109,16 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
     __shared__ double wq[kPW];
     const int tid = threadIdx.x;
     const int w = tid / kPL, l = tid % kPL;
-    int I, J;
-    item_pair(blockIdx.x, ns, I, J);
-    const bool diag = I == J;
+    int I, J;   // super-blocks, relative to their chunks
+    if (pg.tri) {
+        item_pair(blockIdx.x, pg.nsi, I, J);
+    } else {
+        I = (int)(blockIdx.x / pg.nsj);
+        J = (int)(blockIdx.x % pg.nsj);
+    }
+    const bool diag = pg.tri && I == J;
+    I += pg.ci0;
+    J += pg.cj0;
 
     const int64_t jg = (int64_t)J * kPS + tid;
     const bool jok = jg < n;
@@ -275,8 +290,9 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
     }
 }
 
-// Every body's sums: the i-side partials of the items (Kb, J), J = Kb..NS-1,
-// then the j-side partials of the items (I, Kb), I = 0..Kb, in that order.
+// Every body's sums (one launch covering all of them, the triangle of the
+// single chunk): the i-side partials of the items (Kb, J), J = Kb..NS-1, then
+// the j-side partials of the items (I, Kb), I = 0..Kb, in that order.
 __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__restrict__ part,
                                     double *__restrict__ out)
 {
@@ -295,22 +311,100 @@ __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__r
     out[e] = s;
 }
 
+// One launch of a chunked evaluation: adds, for every body of its chunk(s),
+// the partials of that launch's items that hold it (the same order as above
+// within a triangle; J ascending for the i-side and I ascending for the
+// j-side of a rectangle) to out.
+__global__ void reduce_pairs_add_kernel(int64_t n, int nv, PairsGrid pg, const double *__restrict__ part,
+                                        double *__restrict__ out)
+{
+    const int64_t nba = min((int64_t)pg.nsi * kPS, n - (int64_t)pg.ci0 * kPS);
+    const int64_t nbb = pg.tri ? 0 : min((int64_t)pg.nsj * kPS, n - (int64_t)pg.cj0 * kPS);
+    const int64_t nb = nba + nbb;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nv * nb) return;
+    const int comp = (int)(e / nb);
+    const int64_t r = e - (int64_t)comp * nb;
+    const int64_t stride = (int64_t)2 * nv * kPS;
+    double s = 0.0;
+    int64_t body;
+    if (r < nba) {
+        const int kb = (int)(r / kPS), loc = (int)(r % kPS);
+        body = (int64_t)pg.ci0 * kPS + r;
+        if (pg.tri) {
+#pragma unroll 8
+            for (int J = kb; J < pg.nsi; ++J)
+                s += part[item_index(kb, J, pg.nsi) * stride + (int64_t)comp * kPS + loc];
+#pragma unroll 8
+            for (int I = 0; I <= kb; ++I)
+                s += part[item_index(I, kb, pg.nsi) * stride + (int64_t)(nv + comp) * kPS + loc];
+        } else {
+#pragma unroll 8
+            for (int J = 0; J < pg.nsj; ++J)
+                s += part[((int64_t)kb * pg.nsj + J) * stride + (int64_t)comp * kPS + loc];
+        }
+    } else {
+        const int64_t rb = r - nba;
+        const int kb = (int)(rb / kPS), loc = (int)(rb % kPS);
+        body = (int64_t)pg.cj0 * kPS + rb;
+#pragma unroll 8
+        for (int I = 0; I < pg.nsi; ++I)
+            s += part[((int64_t)I * pg.nsj + kb) * stride + (int64_t)(nv + comp) * kPS + loc];
+    }
+    out[(int64_t)comp * n + body] += s;
+}
+
+__global__ void zero_kernel(int64_t count, double *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) out[e] = 0.0;
+}
+
 template <int K, Chain CH, bool QM>
 hipError_t launch_k(const ForceArgs &a, hipStream_t st)
 {
     PPath<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     const int ns = (int)((a.n + kPS - 1) / kPS);
-    const int64_t items = pairs_items(a.n);
-    hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass, path,
-                       a.G, a.eps2, ns, a.partial, a.qpart);
+    const int nv = (K + 1) * 3;
+    if (a.n <= kPairsMaxN) {
+        // one launch: the triangle of all super-blocks
+        const PairsGrid pg{0, ns, 0, ns, 1};
+        const int64_t items = pairs_items(a.n);
+        hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass,
+                           path, a.G, a.eps2, pg, a.partial, a.qpart);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t cnt = (int64_t)nv * a.n;
+        hipLaunchKernelGGL(reduce_pairs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n, nv, ns,
+                           (const double *)a.partial, a.out);
+        return hipGetLastError();
+    }
+    // chunks of cs super-blocks, as large as the workspace holds a rectangle
+    // of (up to 64 x 64 items); chunk pairs in a fixed order, each adding its
+    // partials into the zeroed output
+    const int cs = pairs_chunk(a.partial_cap, K);
+    const int nc = (ns + cs - 1) / cs;
+    const int64_t cnt = (int64_t)nv * a.n;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, cnt, a.out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nv = (K + 1) * 3;
-    const int64_t cnt = (int64_t)nv * a.n;
-    hipLaunchKernelGGL(reduce_pairs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n, nv, ns,
-                       (const double *)a.partial, a.out);
-    return hipGetLastError();
+    for (int A = 0; A < nc; ++A)
+        for (int B = A; B < nc; ++B) {
+            PairsGrid pg{A * cs, min(cs, ns - A * cs), B * cs, min(cs, ns - B * cs), A == B ? 1 : 0};
+            const int64_t items = pg.tri ? (int64_t)pg.nsi * (pg.nsi + 1) / 2 : (int64_t)pg.nsi * pg.nsj;
+            hipLaunchKernelGGL((force_pairs_kernel<K, CH, false>), dim3((unsigned)items), dim3(kPS), 0, st, a.n,
+                               a.mass, path, a.G, a.eps2, pg, a.partial, (double *)nullptr);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const int64_t nb = (int64_t)pg.nsi * kPS + (pg.tri ? 0 : (int64_t)pg.nsj * kPS);
+            const int64_t rc = (int64_t)nv * nb;
+            hipLaunchKernelGGL(reduce_pairs_add_kernel, dim3((unsigned)((rc + 255) / 256)), dim3(256), 0, st, a.n,
+                               nv, pg, (const double *)a.partial, a.out);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 template <Chain CH, bool QM>
@@ -333,12 +427,25 @@ int64_t pairs_items(int64_t n)
 
 int64_t pairs_partial_doubles(int64_t n, int K) { return pairs_items(n) * 2 * (K + 1) * 3 * kPS; }
 
+int pairs_chunk(int64_t partial_cap, int K)
+{
+    const int64_t per_item = (int64_t)2 * (K + 1) * 3 * kPS;
+    int cs = 64;
+    while (cs > 0 && (int64_t)cs * cs * per_item > partial_cap) --cs;
+    return cs;
+}
+
 hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    if (a.k_first != 0 || a.K < 1 || a.K > 3 || a.n > kPairsMaxN) return hipErrorInvalidValue;
-    if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
+    if (a.k_first != 0 || a.K < 1 || a.K > 3) return hipErrorInvalidValue;
     const bool qm = a.qpart != nullptr;
+    if (a.n <= kPairsMaxN) {
+        if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
+    } else {
+        // chunked: no fused rate; chunks of at least 16 super-blocks
+        if (qm || pairs_chunk(a.partial_cap, a.K) < kPairsMinChunk) return hipErrorInvalidValue;
+    }
     if (qm) {
         if (pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
         if (a.q_count) *a.q_count = (int)pairs_items(a.n);

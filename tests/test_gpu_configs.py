@@ -24,10 +24,12 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _gpu_eval(order, w, path, precision, eps2):
+def _gpu_eval(order, w, path, precision, eps2, launch=None):
     p = order // 2 - 1
     n = len(w["mass"])
     h = Hermite(order, n, precision=precision, eps2=eps2, device=DEV)
+    if launch is not None:
+        h.set_launch(*launch)
     st = h.state(w["mass"], w["x"], w["v"])
     for k in range(p + 1):
         st.pred[k].copy_(torch.as_tensor(np.ascontiguousarray(path[k])))
@@ -42,10 +44,12 @@ def cluster():
     return plummer_cluster()
 
 
+@pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_plummer_cluster_full_size(cluster, precision):
-    # 131072 stars + a central mass 0.01, 6th order (a, adot, a^(2)), eps = 1e-4
-    _say("plummer cluster N=%d %s" % (len(cluster["mass"]), precision))
+def test_plummer_cluster_full_size(cluster, precision, launch):
+    # 131072 stars + a central mass 0.01, 6th order (a, adot, a^(2)), eps = 1e-4;
+    # the default launch and every pair once (in chunks)
+    _say("plummer cluster N=%d %s launch=%s" % (len(cluster["mass"]), precision, launch))
     w = cluster
     ap = 3.0 * np.pi / 16.0
     x = w["x"]
@@ -55,7 +59,7 @@ def test_plummer_cluster_full_size(cluster, precision):
     il = np.sort(rng.choice(len(w["mass"]), 256, replace=False))
     il[-1] = len(w["mass"]) - 1               # the central mass
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=2, eps2=w["eps2"], i_list=il, with_mag=True, with_scale=True)
-    g = _gpu_eval(6, w, path, precision, w["eps2"])[:, :, il]
+    g = _gpu_eval(6, w, path, precision, w["eps2"], launch)[:, :, il]
     if precision == "fp64":
         err = deriv_error(g, o, mag)
         assert within(err, TOL_FP64), err.max(axis=1)
@@ -70,10 +74,12 @@ def big_disc():
     return large_disc()
 
 
+@pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_large_disc_full_size(big_disc, precision):
-    # 1048576 bodies, 8th order (a .. a^(3)), one evaluation, 128 sampled i
-    _say("large disc N=%d %s" % (len(big_disc["mass"]), precision))
+def test_large_disc_full_size(big_disc, precision, launch):
+    # 1048576 bodies, 8th order (a .. a^(3)), one evaluation, 128 sampled i;
+    # the default launch and every pair once (in chunks)
+    _say("large disc N=%d %s launch=%s" % (len(big_disc["mass"]), precision, launch))
     w = big_disc
     x, v = w["x"], w["v"]
     r2 = np.sum(x * x, axis=0)
@@ -85,7 +91,7 @@ def test_large_disc_full_size(big_disc, precision):
     il = np.sort(rng.choice(len(w["mass"]), 128, replace=False))
     il[0] = 0
     o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
-    g = _gpu_eval(8, w, path, precision, 0.0)[:, :, il]
+    g = _gpu_eval(8, w, path, precision, 0.0, launch)[:, :, il]
     if precision == "fp64":
         err = deriv_error(g, o, mag)
         assert within(err, TOL_FP64), err.max(axis=1)

@@ -174,16 +174,41 @@ def test_pairs_once_limits():
         with pytest.raises(HermiteError):
             h.set_launch(*bad)
     h.close()
-    # above 32768 bodies the evaluation refuses the shape (E_ARG), in-range it runs
-    n = 32769
-    rng = np.random.default_rng(3)
-    h = Hermite(4, n, device=DEV)
-    st = h.state(np.full(n, 1.0 / n), rng.normal(size=(3, n)), np.zeros((3, n)))
-    h.set_launch(*PAIRS)
-    with pytest.raises(HermiteError) as ei:
-        h.force_derivs(st)
-    assert ei.value.status == -1
-    h.close()
+
+
+def _kepler_path(w, K):
+    # the central body's Kepler field as the path's a and adot
+    x, v = w["x"], w["v"]
+    r2 = np.sum(x * x, axis=0)
+    rv = np.sum(x * v, axis=0)
+    path = [x, v, -x * r2 ** -1.5, -v * r2 ** -1.5 + 3.0 * x * rv * r2 ** -2.5]
+    path[2][:, 0] = 0.0
+    path[3][:, 0] = 0.0
+    return path[:K + 1]
+
+
+@pytest.mark.parametrize("order,n", [(4, 32769), (8, 40000), (6, 50000)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
+def test_force_derivs_pairs_once_chunked(order, n, precision):
+    # beyond 32768 bodies: chunks of up to 64 super-blocks, one launch per
+    # chunk pair (triangles and rectangles, a last chunk of 1 super-block at
+    # n = 32769 and partial ones otherwise); sampled i against the oracle,
+    # and the FP64 result against the LDS kernel's
+    _say("pairs-once chunked order=%d n=%d %s" % (order, n, precision))
+    p = order // 2 - 1
+    w = disc16k(n)
+    path = _kepler_path(w, p)
+    rng = np.random.default_rng(n)
+    il = np.sort(rng.choice(n, 160, replace=False))
+    il[0], il[-1] = 0, n - 1
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, i_list=il, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, w["mass"], path, precision, launch=PAIRS)
+    assert _pairs_ok(g[:, :, il], o, mag, nat, precision)
+    if precision == "fp64":
+        ref = _eval_gpu(order, w["mass"], path, "fp64", launch=(2, 4, 0, 4))
+        scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+        assert (np.abs(g - ref) / scale).max() <= 1e-13
+        assert np.array_equal(g, _eval_gpu(order, w["mass"], path, precision, launch=PAIRS))
 
 
 def test_set_launch_validation():
