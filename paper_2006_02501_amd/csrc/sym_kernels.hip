@@ -28,6 +28,8 @@
 // the result is bitwise reproducible.  The partials take 2 * 12 * 256 doubles
 // per item, about N^2 / 2700 doubles in all (100 MB at N = 16384), so this
 // path is offered for N up to kPairsMaxN.
+#include <type_traits>
+
 #include "force_launch.h"
 #include "pair_chain.h"
 
@@ -96,7 +98,10 @@ struct PairsGrid {
 };
 
 template <int K, Chain CH, bool QM>
-__global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
+// Three workgroups per CU fit the LDS; the register cap that lets them all be
+// resident costs the 8th-order FP64 kernel a few spilled bytes and is still
+// faster (609 against 637 us on the 16k disc) than two per CU.
+__global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
                                                           double G, double eps2, PairsGrid pg,
                                                           double *__restrict__ part, double *__restrict__ qpart)
 {
@@ -147,8 +152,10 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
             accf_i[k][c] = 0.0f;
         }
     double qmax = 0.0;
-    // j-bodies of super-block J that exist
+    // j-bodies of super-block J that exist; an item with padding bodies on
+    // either side (the last super-block of a ragged n) masks their lanes
     const int jvalid = (int)min((int64_t)kPS, n - (int64_t)J * kPS);
+    const bool edge = jvalid < kPS || (int64_t)(I + 1) * kPS > n;
     __syncthreads();
 
     const int nphase = diag ? 3 : kPW;
@@ -166,78 +173,104 @@ __global__ __launch_bounds__(kPS) void force_pairs_kernel(int64_t n, const doubl
                     accf_j[k][c] = 0.0f;
                 }
             const int t0 = same ? 1 : 0, t1 = same ? kPL / 2 : kPL - 1;
-            for (int tc = t0; tc <= t1; tc += kFoldSteps) {
-                const int te = min(t1, tc + kFoldSteps - 1);
-                for (int t = tc; t <= te; ++t) {
-                    const int js = v * kPL + ((l + t) & (kPL - 1));
-                    const bool ok = iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2);
-                    if constexpr (CH == Chain::Mixed) {
-                        float r[3], vv[3], a[3], jk[3];
-                        double r64[3];
+            // one sweep step; MASKED: some lanes may have to drop their pair
+            auto step = [&](int t, auto masked) {
+                const int js = v * kPL + ((l + t) & (kPL - 1));
+                // (unmasked steps: every lane's pair counts)
+                const bool ok = !decltype(masked)::value ||
+                                (iok && js < jvalid && !(same && t == kPL / 2 && l >= kPL / 2));
+                // relative path (FP64 differences)
+                double d[K + 1][3];
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            r64[c] = sj[1 + c][js] - xi[0][c];
-                            r[c] = (float)r64[c];
-                            vv[c] = (float)(sj[4 + c][js] - xi[1][c]);
-                            if constexpr (K >= 2) a[c] = (float)(sj[7 + c][js] - xi[2][c]); else a[c] = 0.0f;
-                            if constexpr (K >= 3) jk[c] = (float)(sj[10 + c][js] - xi[3][c]); else jk[c] = 0.0f;
-                        }
-                        float w2 = __builtin_fmaf(r[0], r[0],
-                                                  __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], (float)eps2)));
-                        w2 = ok ? w2 : 1.0f;
-                        const float rinv = rsqrt32(w2);
-                        const float rinv2 = rinv * rinv;
-                        const float q3 = ok ? rinv * rinv2 : 0.0f;
-                        if constexpr (QM) {
-                            // the step criterion's rate, from the FP64 differences
-                            double w64 = __builtin_fma(r64[0], r64[0],
-                                                       __builtin_fma(r64[1], r64[1], __builtin_fma(r64[2], r64[2], eps2)));
-                            w64 = ok ? w64 : 1.0;
-                            const double y = rsqrt64(w64);
-                            qmax = __builtin_fmax(qmax, ok ? (gmi + sj[0][js]) * (y * y * y) : 0.0);
-                        }
-                        chain_pair<K, float>(r, vv, a, jk, sjm[js] * q3, -gmif * q3, rinv2, accf_i, accf_j);
-                    } else {
-                        double r[3], vv[3];
+                for (int k = 0; k <= K; ++k)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            r[c] = sj[1 + c][js] - xi[0][c];
-                            vv[c] = sj[4 + c][js] - xi[1][c];
-                        }
-                        double w2 =
-                            __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
-                        w2 = ok ? w2 : 1.0;
-                        const double rinv = rsqrt64(w2);
-                        const double rinv2 = rinv * rinv;
-                        const double q3 = ok ? rinv * rinv2 : 0.0;
-                        const double gmj = sj[0][js];
-                        if constexpr (QM) qmax = __builtin_fmax(qmax, (gmi + gmj) * q3);
-                        if constexpr (CH == Chain::Split) {
-                            float a[3], jk[3];
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                a[c] = (float)(sj[7 + c][js] - xi[2][c]);
-                                if constexpr (K >= 3) jk[c] = (float)(sj[10 + c][js] - xi[3][c]); else jk[c] = 0.0f;
-                            }
-                            chain_split_pair<K>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j, accf_i,
-                                                accf_j);
-                        } else {
-                            double a[3], jk[3];
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                if constexpr (K >= 2) a[c] = sj[7 + c][js] - xi[2][c]; else a[c] = 0.0;
-                                if constexpr (K >= 3) jk[c] = sj[10 + c][js] - xi[3][c]; else jk[c] = 0.0;
-                            }
-                            chain_pair<K, double>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j);
-                        }
-                    }
+                    for (int c = 0; c < 3; ++c) d[k][c] = sj[1 + 3 * k + c][js] - xi[k][c];
+                if constexpr (decltype(masked)::value) {
+                    // a lane that must not count its pair (a padding body, or
+                    // the second half of step 32) takes a zero path, so its
+                    // chain is exactly zero: evaluated at w = 1 on the real
+                    // differences it could overflow FP32 and give 0 * inf
 #pragma unroll
                     for (int k = 0; k <= K; ++k)
 #pragma unroll
+                        for (int c = 0; c < 3; ++c) d[k][c] = ok ? d[k][c] : 0.0;
+                }
+                if constexpr (CH == Chain::Mixed) {
+                    float r[3], vv[3], a[3], jk[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = (float)d[0][c];
+                        vv[c] = (float)d[1][c];
+                        if constexpr (K >= 2) a[c] = (float)d[K >= 2 ? 2 : 0][c]; else a[c] = 0.0f;
+                        if constexpr (K >= 3) jk[c] = (float)d[K >= 3 ? 3 : 0][c]; else jk[c] = 0.0f;
+                    }
+                    float w2 = __builtin_fmaf(r[0], r[0],
+                                              __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], (float)eps2)));
+                    w2 = ok ? w2 : 1.0f;
+                    const float rinv = rsqrt32(w2);
+                    const float rinv2 = rinv * rinv;
+                    const float q3 = ok ? rinv * rinv2 : 0.0f;
+                    if constexpr (QM) {
+                        // the step criterion's rate, from the FP64 differences
+                        double w64 = __builtin_fma(d[0][0], d[0][0],
+                                                   __builtin_fma(d[0][1], d[0][1], __builtin_fma(d[0][2], d[0][2], eps2)));
+                        w64 = ok ? w64 : 1.0;
+                        const double y = rsqrt64(w64);
+                        qmax = __builtin_fmax(qmax, ok ? (gmi + sj[0][js]) * (y * y * y) : 0.0);
+                    }
+                    chain_pair<K, float>(r, vv, a, jk, sjm[js] * q3, -gmif * q3, rinv2, accf_i, accf_j);
+                } else {
+                    double r[3], vv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = d[0][c];
+                        vv[c] = d[1][c];
+                    }
+                    double w2 =
+                        __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
+                    w2 = ok ? w2 : 1.0;
+                    const double rinv = rsqrt64(w2);
+                    const double rinv2 = rinv * rinv;
+                    const double q3 = ok ? rinv * rinv2 : 0.0;
+                    const double gmj = sj[0][js];
+                    if constexpr (QM) qmax = __builtin_fmax(qmax, (gmi + gmj) * q3);
+                    if constexpr (CH == Chain::Split) {
+                        float a[3], jk[3];
+#pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            if (k < F) acc_j[k][c] = lane_down(acc_j[k][c]);
-                            else accf_j[k][c] = lane_down(accf_j[k][c]);
+                            a[c] = (float)d[K >= 2 ? 2 : 0][c];
+                            if constexpr (K >= 3) jk[c] = (float)d[K >= 3 ? 3 : 0][c]; else jk[c] = 0.0f;
                         }
+                        chain_split_pair<K>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j, accf_i,
+                                            accf_j);
+                    } else {
+                        double a[3], jk[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if constexpr (K >= 2) a[c] = d[K >= 2 ? 2 : 0][c]; else a[c] = 0.0;
+                            if constexpr (K >= 3) jk[c] = d[K >= 3 ? 3 : 0][c]; else jk[c] = 0.0;
+                        }
+                        chain_pair<K, double>(r, vv, a, jk, gmj * q3, -gmi * q3, rinv2, acc_i, acc_j);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (k < F) acc_j[k][c] = lane_down(acc_j[k][c]);
+                        else accf_j[k][c] = lane_down(accf_j[k][c]);
+                    }
+                            };
+            for (int tc = t0; tc <= t1; tc += kFoldSteps) {
+                const int te = min(t1, tc + kFoldSteps - 1);
+                if (edge) {
+                    for (int t = tc; t <= te; ++t) step(t, std::true_type{});
+                } else {
+                    // the diagonal sweep's last step (32) counts its pairs on
+                    // lanes 0..31 only
+                    const int tn = (same && te == kPL / 2) ? te - 1 : te;
+                    for (int t = tc; t <= tn; ++t) step(t, std::false_type{});
+                    if (tn < te) step(te, std::true_type{});
                 }
                 if constexpr (F <= K) {
                     // fold the FP32 sums of these steps: the i-side into its FP64

@@ -166,6 +166,25 @@ def test_force_derivs_pairs_once_largest(precision):
         assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
+def test_pairs_once_masked_lanes_stay_finite(precision):
+    # Bodies 1e4 apart whose path adot is ~1e33: every real pair's chain fits
+    # FP32 (it is scaled by 1/r^2 ~ 1e-8), but a lane that must drop its pair
+    # (the second half of the diagonal block's step 32, or a padding body of
+    # the ragged last super-block) would overflow FP32 at w = 1 and put
+    # 0 * inf = NaN into real sums.  Such lanes take a zero path instead.
+    _say("pairs-once masked lanes %s" % precision)
+    n = 300                      # a full super-block and a ragged one
+    rng = np.random.default_rng(21)
+    mass = rng.uniform(0.5, 1.5, n)
+    path = [rng.uniform(-1e4, 1e4, (3, n)), rng.normal(size=(3, n)) * 1e3,
+            rng.normal(size=(3, n)) * 1e10, rng.normal(size=(3, n)) * 1e33]
+    o, mag, nat = ho.pair_derivs(mass, path, K=3, with_mag=True, with_scale=True)
+    g = _eval_gpu(8, mass, path, precision, launch=PAIRS)
+    assert np.all(np.isfinite(g))
+    assert _pairs_ok(g, o, mag, nat, precision)
+
+
 def test_pairs_once_limits():
     _say("pairs-once limits")
     from paper_2006_02501_amd import HermiteError
