@@ -40,7 +40,7 @@ KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_025
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "892b8629d1039b5bea19603535e506687936ebfba87cbe98bf2e1cad764530c4",
+        "sources_sha256": "1cd176900ac8f4a33bc598d275b5ca9218ceeb0c2af5b9d775d11366544be3b7",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -51,7 +51,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 118443022
     },
     "mixed": {
-        "sources_sha256": "892b8629d1039b5bea19603535e506687936ebfba87cbe98bf2e1cad764530c4",
+        "sources_sha256": "1cd176900ac8f4a33bc598d275b5ca9218ceeb0c2af5b9d775d11366544be3b7",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -62,7 +62,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "892b8629d1039b5bea19603535e506687936ebfba87cbe98bf2e1cad764530c4",
+        "sources_sha256": "1cd176900ac8f4a33bc598d275b5ca9218ceeb0c2af5b9d775d11366544be3b7",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,

@@ -26,8 +26,10 @@
 // super-block J (partial sums in HBM); a second kernel adds, for every body,
 // the partials of the items that hold it, in a fixed order.  No atomics:
 // the result is bitwise reproducible.  The partials take 2 * 12 * 256 doubles
-// per item, about N^2 / 2700 doubles in all (100 MB at N = 16384), so this
-// path is offered for N up to kPairsMaxN.
+// per item, about N^2 / 2700 doubles in all (100 MB at N = 16384), so one
+// launch covers at most kPairsMaxN bodies; beyond that the bodies are cut into
+// chunks and every pair of chunks is one launch (a triangle or a rectangle of
+// items) whose partials are added to the output in a fixed order.
 #include <type_traits>
 
 #include "force_launch.h"
@@ -97,10 +99,10 @@ struct PairsGrid {
     int tri;
 };
 
-template <int K, Chain CH, bool QM>
 // Three workgroups per CU fit the LDS; the register cap that lets them all be
 // resident costs the 8th-order FP64 kernel a few spilled bytes and is still
 // faster (609 against 637 us on the 16k disc) than two per CU.
+template <int K, Chain CH, bool QM>
 __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
                                                           double G, double eps2, PairsGrid pg,
                                                           double *__restrict__ part, double *__restrict__ qpart)

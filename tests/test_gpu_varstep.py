@@ -192,6 +192,27 @@ def test_fused_rate_pairs_once(nb):
     assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
 
 
+def test_chunked_pairs_symmetric_step_matches_lds():
+    # beyond 32768 bodies the every-pair-once evaluation runs in chunks and
+    # keeps no rate, so the variable step takes the separate criterion pass;
+    # its steps must match those of the LDS kernel (which fuses the rate)
+    _say("symmetric step, chunked pairs vs LDS, n=33000")
+    n = 33000
+    w, _ = disc_path(n, 1)
+    out = {}
+    for name, launch in (("lds", (2, 4, 0, 4)), ("pairs", (1, 0, 2, 4))):
+        h = Hermite(4, n, eps2=1e-10, device=DEV)
+        h.set_launch(*launch)
+        st = h.state(w["mass"], w["x"], w["v"])
+        h.init(st)
+        dts = [h.step_symmetric(st, 0.05, 3) for _ in range(3)]
+        out[name] = (np.array(dts), st.host())
+        h.close()
+    (da, ga), (db, gb) = out["lds"], out["pairs"]
+    assert np.max(np.abs(db / da - 1.0)) <= 1e-13, (da, db)
+    assert rel_max(gb["x"], ga["x"]) <= 1e-13 and rel_max(gb["v"], ga["v"]) <= 1e-13
+
+
 @pytest.mark.parametrize("launch", [None, (1, 0, 2, 4)])
 def test_mixed_symmetric_step_within_force_bound(launch):
     # The mixed evaluation's relative force error delta (<= 1e-6, the bar of
