@@ -7,10 +7,11 @@
 // state (x, v, a^(0..2p-1)) in VGPRs for all steps, and exchanges the
 // predicted / corrected path of the current iterate through LDS.  The only
 // global traffic per bin is the initial load, the final store and one counter
-// increment.  Lanes of different systems in one bin loop over their own
-// system's slots; an exhausted or idle lane contributes zero.  Systems may
-// take different iteration counts n: a bin iterates as often as its largest
-// n, and a system stops correcting (and keeps its last iterate) after its own.
+// increment.  An evaluation takes each pair of a system once, for both of its
+// bodies, in a sweep over the bin's lanes (see the kernel); an idle lane, or a
+// lane without a pair in a sweep step, contributes zero.  Systems may take
+// different iteration counts n: a bin iterates as often as its largest n, and
+// a system stops correcting (and keeps its last iterate) after its own.
 #include "hermite_coeffs.h"
 #include "kernels.h"
 #include "pair_chain.h"
@@ -99,6 +100,40 @@ __global__ __launch_bounds__(kLanes) void batch_init_kernel(BatchPlan pl, int64_
     }
 }
 
+// Cross-lane moves of the j-side sums: one lane down the whole wave (DPP
+// rotate: lane l takes lane l + 1's value, lane 63 lane 0's), or from any
+// lane (ds_bpermute; addr = 4 x source lane).
+__device__ __forceinline__ double lane_down(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float lane_down(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double lane_from(int addr, double x)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float lane_from(int addr, float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
+
+// Bins whose largest system has at least this many bodies sweep the whole
+// wave as one ring: 32 steps, sums moved by DPP.  The others sweep each system
+// as a ring of its own: largest/2 steps, sums moved by permutes, which go
+// through the LDS unit and make a step about a third dearer with two waves
+// per SIMD.  The measured break-even lies between 41 and 57 bodies.
+constexpr int kRingMin = 49;
+
 __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
 
 __device__ constexpr double kInvB[9] = {0.0, 1.0, 1.0 / 2.0, 1.0 / 3.0, 1.0 / 4.0, 1.0 / 5.0, 1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0};
@@ -112,15 +147,17 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                                                            double eps2, double *__restrict__ comp)
 {
     constexpr int K = P;
-    // the 8th-order FP64 kernel with compensation would exceed 256 registers
-    constexpr int kPairUnroll = (P == 3 && !MIXED && COMP) ? 1 : 2;
-    __shared__ double sm[kLanes];
-    __shared__ float smf[kLanes];
+    // chain arithmetic: FP64, or FP32 from the FP64 differences (mixed)
+    using T = typename std::conditional<MIXED, float, double>::type;
+    // two sweep steps in flight; the 8th-order FP64 kernel with compensation
+    // would exceed 256 registers with them
+    constexpr bool kTwoSteps = !(P == 3 && !MIXED && COMP);
+    __shared__ T sgm[kLanes];
     __shared__ double sp[K + 1][3][kLanes];
+    __shared__ double wait_xv[COMP ? 12 : 1][kLanes];
     __shared__ int next_bin;
     const int lane = threadIdx.x;
     const int64_t n3 = 3 * n;
-    const float eps2f = (float)eps2;
 
     for (;;) {
         if (lane == 0) next_bin = atomicAdd(pl.counter, 1);
@@ -164,8 +201,18 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
             }
         }
         const double gm = active ? G * mass[li.g] : 0.0;
-        sm[lane] = gm;
-        smf[lane] = (float)gm;
+        const T gm_own = (T)gm;
+        sgm[lane] = gm_own;
+        // The bin's sweep (every pair of each system once, see below): its
+        // kind, its step count, the lane a segment sweep passes sums from, and
+        // the lane holding this body's j-side sums after the sweep.
+        const int sz = li.hi - li.lo, q = lane - li.lo, half = sz / 2;
+        const bool ring = li.maxlen >= kRingMin;
+        const int nsweep = ring ? min(li.maxlen - 1, kLanes / 2) : li.maxlen / 2;
+        const int succ = 4 * (li.lo + (q + 1 == sz ? 0 : q + 1));
+        int hq = q - nsweep % sz;
+        hq = hq < 0 ? hq + sz : hq;
+        const int home = 4 * (ring ? ((lane - nsweep) & (kLanes - 1)) : li.lo + hq);
 
         for (int step = 0; step < n_steps; ++step) {
             // Taylor predictor from the t0 state (Horner form).
@@ -195,61 +242,100 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
 #pragma unroll
                     for (int c = 0; c < 3; ++c) sp[k][c][lane] = path[k][c];
                 __syncthreads();
-                // Evaluate a^(0..P) over the lane's own system.
-                double acc[K + 1][3];
-                float accf[K + 1][3];
+                // Evaluate a^(0..P) over the lane's own system, every pair
+                // once: the pair's chain adds to this lane's sums (the i-side)
+                // and, with the opposite sign and the other mass, to sums that
+                // travel with the partner (the j-side), passed one lane on
+                // between steps; after the sweep they go back to their body.
+                //  - ring: the whole wave is one ring; in step t = 1..nsweep
+                //    lane l takes lane l + t (mod 64) if it is of the same
+                //    system (at t = 32 only from lanes 0..31).  A system is
+                //    contiguous, so each of its pairs is at ring distance
+                //    <= min(maxlen - 1, 32) one way round.
+                //  - segments: each system is a ring of its own; in step
+                //    t = 1..sz/2 local body q takes q + t (mod sz) (at t = sz/2
+                //    of an even sz only from its first half).
+                T acc[K + 1][3], accj[K + 1][3];
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        acc[k][c] = 0.0;
-                        accf[k][c] = 0.0f;
+                        acc[k][c] = T(0);
+                        accj[k][c] = T(0);
                     }
-                // two pair chains in flight per lane: one wave alone on a SIMD
-                // is latency-bound (same summation order)
-#pragma unroll kPairUnroll
-                for (int t = 0; t < li.maxlen; ++t) {
-                    const int j = li.lo + t;
-                    const bool act = active && j < li.hi && j != lane;
-                    const int jc = act ? j : lane;
-                    if constexpr (!MIXED) {
-                        double r[3], vv[3], aa[3], jj[3];
+                // the sweep, RING a compile-time tag (one loop per kind)
+                auto sweep = [&](auto ring_tag) {
+                    constexpr bool RING = decltype(ring_tag)::value;
+                    auto step = [&](int t) {
+                        int jc;
+                        bool act;
+                        if constexpr (RING) {
+                            const int pl = (lane + t) & (kLanes - 1);
+                            act = pl >= li.lo && pl < li.hi && !(t == kLanes / 2 && lane >= kLanes / 2);
+                            jc = pl;
+                        } else {
+                            int q2 = q + t;
+                            q2 = q2 >= sz ? q2 - sz : q2;
+                            act = t <= half && !(2 * t == sz && q >= half);
+                            jc = li.lo + q2;
+                        }
+                        jc = act ? jc : lane;   // no pair: zero differences, zero weight
+                        T r[3], vv[3], aa[3], jj[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            r[c] = sp[0][c][jc] - path[0][c];
-                            vv[c] = sp[1][c][jc] - path[1][c];
-                            aa[c] = K >= 2 ? sp[K >= 2 ? 2 : 0][c][jc] - path[K >= 2 ? 2 : 0][c] : 0.0;
-                            jj[c] = K >= 3 ? sp[K >= 3 ? 3 : 0][c][jc] - path[K >= 3 ? 3 : 0][c] : 0.0;
+                            r[c] = (T)(sp[0][c][jc] - path[0][c]);
+                            vv[c] = (T)(sp[1][c][jc] - path[1][c]);
+                            aa[c] = K >= 2 ? (T)(sp[K >= 2 ? 2 : 0][c][jc] - path[K >= 2 ? 2 : 0][c]) : T(0);
+                            jj[c] = K >= 3 ? (T)(sp[K >= 3 ? 3 : 0][c][jc] - path[K >= 3 ? 3 : 0][c]) : T(0);
                         }
-                        double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], eps2)));
-                        w = act ? w : 1.0;
-                        const double m = act ? sm[jc] : 0.0;
-                        const double rinv = rsqrt64(w);
-                        const double rinv2 = rinv * rinv;
-                        chain_accumulate<K, double>(r, vv, aa, jj, m * rinv * rinv2, rinv2, acc);
-                    } else {
-                        float r[3], vv[3], aa[3], jj[3];
+                        T w = fma_t(r[0], r[0], fma_t(r[1], r[1], fma_t(r[2], r[2], (T)eps2)));
+                        w = act ? w : T(1);
+                        const T rinv = rsqrt_t(w);
+                        const T rinv2 = rinv * rinv;
+                        const T q3 = act ? rinv * rinv2 : T(0);
+                        chain_pair<K, T>(r, vv, aa, jj, sgm[jc] * q3, -gm_own * q3, rinv2, acc, accj);
+                    };
+                    auto pass_on = [&]() {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            r[c] = (float)(sp[0][c][jc] - path[0][c]);
-                            vv[c] = (float)(sp[1][c][jc] - path[1][c]);
-                            aa[c] = K >= 2 ? (float)(sp[K >= 2 ? 2 : 0][c][jc] - path[K >= 2 ? 2 : 0][c]) : 0.0f;
-                            jj[c] = K >= 3 ? (float)(sp[K >= 3 ? 3 : 0][c][jc] - path[K >= 3 ? 3 : 0][c]) : 0.0f;
-                        }
-                        float w = __builtin_fmaf(r[0], r[0], __builtin_fmaf(r[1], r[1], __builtin_fmaf(r[2], r[2], eps2f)));
-                        w = act ? w : 1.0f;
-                        const float m = act ? smf[jc] : 0.0f;
-                        const float rinv = rsqrt32(w);
-                        const float rinv2 = rinv * rinv;
-                        chain_accumulate<K, float>(r, vv, aa, jj, m * rinv * rinv2, rinv2, accf);
+                        for (int k = 0; k <= K; ++k)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                if constexpr (RING) accj[k][c] = lane_down(accj[k][c]);
+                                else accj[k][c] = lane_from(succ, accj[k][c]);
+                            }
+                    };
+                    int t = 1;
+                    if (nsweep >= 1) {
+                        step(1);
+                        t = 2;
                     }
-                }
+                    if constexpr (kTwoSteps) {
+                        for (; t + 1 <= nsweep; t += 2) {
+                            pass_on();
+                            step(t);
+                            pass_on();
+                            step(t + 1);
+                        }
+                    }
+                    for (; t <= nsweep; ++t) {
+                        pass_on();
+                        step(t);
+                    }
+                };
+                if (ring) sweep(std::true_type{});
+                else sweep(std::false_type{});
+                // lane l now holds the j-side sums of body l + nsweep (ring) or
+                // of local body q + nsweep (segments)
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) accj[k][c] = lane_from(home, accj[k][c]);
                 // a system past its own iteration count keeps its last iterate
                 if (it >= my_iter) continue;
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) a1[k][c] = MIXED ? (double)accf[k][c] : acc[k][c];
+                    for (int c = 0; c < 3; ++c) a1[k][c] = (double)acc[k][c] + (double)accj[k][c];
                 // Modified corrector: velocity first, then position.
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -289,6 +375,27 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
 #pragma unroll
                         for (int m = 0; m <= K - 2; ++m) path[2 + m][c] = a1[m][c];
                     }
+                }
+                if constexpr (COMP) {
+                    // with compensation the iterate's x, v and their new
+                    // compensation terms wait in LDS (this lane's slots) over
+                    // later iterations: registers stay within 256
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        wait_xv[c][lane] = x1[c];
+                        wait_xv[3 + c][lane] = v1[c];
+                        wait_xv[6 + c][lane] = ncx[c];
+                        wait_xv[9 + c][lane] = ncv[c];
+                    }
+                }
+            }
+            if constexpr (COMP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x1[c] = wait_xv[c][lane];
+                    v1[c] = wait_xv[3 + c][lane];
+                    ncx[c] = wait_xv[6 + c][lane];
+                    ncv[c] = wait_xv[9 + c][lane];
                 }
             }
             // End of step: interpolated higher derivatives, then the new state.

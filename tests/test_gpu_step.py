@@ -271,6 +271,51 @@ def test_batch_matches_oracle(batch_workload, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_sweep_kinds_match_oracle(batch_workload, precision):
+    # Sizes chosen so that the packed bins take both sweeps of the batched
+    # evaluation and their edge cases: whole-wave rings (a 64-body system
+    # alone, with its 32nd step from half the lanes; 50 + 14 and 49 + 15, the
+    # small system sitting at the end of the ring) and per-system rings
+    # (48 + 16 and 33 + 31, even sizes with a half last step; 7 + 3 + 2 + 1,
+    # including a two-body and a one-body system).
+    _say("batch sweep kinds %s" % precision)
+    wb = batch_workload
+    offs = wb["offsets"]
+    sizes = np.diff(offs)
+    want = [64, 50, 14, 49, 15, 48, 16, 33, 31, 7, 3, 2, 1]
+    mass, xs, vs, dts, parts = [], [], [], [], []
+    for n in want:
+        s = int(np.nonzero(sizes == max(n, 3))[0][0])
+        lo = offs[s]
+        mass.append(wb["mass"][lo:lo + n])
+        xs.append(wb["x"][:, lo:lo + n])
+        vs.append(wb["v"][:, lo:lo + n])
+        dts.append(wb["dt"][s])
+    off = np.concatenate([[0], np.cumsum(want)]).astype(np.int64)
+    mass = np.concatenate(mass)
+    x = np.ascontiguousarray(np.concatenate(xs, axis=1))
+    v = np.ascontiguousarray(np.concatenate(vs, axis=1))
+    dts = np.array(dts)
+    bh = BatchHermite(8, off, precision=precision, device=DEV)
+    st = bh.state(mass, x, v)
+    bh.init(st)
+    steps = 10
+    bh.run(st, dts, steps, 3)
+    d = st.host()
+    bh.close()
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    for k, n in enumerate(want):
+        lo, hi = off[k], off[k + 1]
+        o = ho.State(mass[lo:hi], x[:, lo:hi], v[:, lo:hi], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, dts[k], 3)
+        assert np.all(np.isfinite(d["x"][:, lo:hi])), n
+        assert rel_max(d["x"][:, lo:hi], o.x) <= tol, n
+        assert rel_max(d["v"][:, lo:hi], o.v) <= tol * 10, n
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_full_size_sampled(batch_workload, precision):
     # all 4096 systems in one launch, as the benchmark runs them (default
     # persistent grid, graph capture); sampled systems against the oracle:
