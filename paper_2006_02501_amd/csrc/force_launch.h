@@ -59,14 +59,21 @@ int auto_split(int64_t n, const LaunchShape &shape, bool generic);
 // k_first = 0): work items are pairs of 256-body super-blocks, each writing
 // 2 * (K+1) * 3 * 256 partial sums into a.partial, which a fixed-order
 // reduction adds into a.out.  Up to kPairsMaxN bodies one launch covers all
-// pairs; with a.qpart it also writes one pair-rate maximum per item
-// (a.q_count = the item count), from FP64 differences in every chain.
+// pairs, with one workgroup per item and phase when the items are few
+// (pairs_split) and a.partial (and a.qpart) hold them; with a.qpart it also
+// writes one pair-rate maximum per workgroup (a.q_count = the workgroup
+// count), from FP64 differences in every chain.
 // Beyond kPairsMaxN the bodies are cut into chunks of pairs_chunk()
 // super-blocks (at least kPairsMinChunk) and each chunk pair is one launch
 // whose partials are added to the output in a fixed order (no rate).
 constexpr int64_t kPairsMaxN = 32768;
 constexpr int kPairsMinChunk = 16;
 int64_t pairs_items(int64_t n);
+// Items are split by phase when at most half as many as the `slots`
+// workgroups the GPU holds at once.
+bool pairs_split(int64_t items, int64_t slots);
+// Partial sums a single launch may write, split items included (the device's
+// resident-workgroup counts are queried on the current device).
 int64_t pairs_partial_doubles(int64_t n, int K);
 // Super-blocks per chunk whose rectangle of items fits partial_cap (<= 64).
 int pairs_chunk(int64_t partial_cap, int K);

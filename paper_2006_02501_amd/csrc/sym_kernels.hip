@@ -25,11 +25,19 @@
 // Outputs per item: the i-side sums of super-block I and the j-side sums of
 // super-block J (partial sums in HBM); a second kernel adds, for every body,
 // the partials of the items that hold it, in a fixed order.  No atomics:
-// the result is bitwise reproducible.  The partials take 2 * 12 * 256 doubles
+// the result is bitwise reproducible.  A launch of few items (at most half
+// as many as the GPU holds at once, up to ~6900 bodies) takes one workgroup
+// per item and phase instead, each writing its own partials: four times the
+// workgroups for a GPU that would otherwise run latency-bound.  With two or
+// more waves per SIMD a SIMD issues nearly as fast as with three, so larger
+// launches, partial last round included, gain nothing from it (measured at
+// 8k-32k bodies).  The partials take 2 * 12 * 256 doubles
 // per item, about N^2 / 2700 doubles in all (100 MB at N = 16384), so one
 // launch covers at most kPairsMaxN bodies; beyond that the bodies are cut into
 // chunks and every pair of chunks is one launch (a triangle or a rectangle of
 // items) whose partials are added to the output in a fixed order.
+#include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "force_launch.h"
@@ -41,6 +49,7 @@ namespace {
 constexpr int kPW = 4;             // waves per workgroup = j-blocks per super-block
 constexpr int kPL = 64;            // lanes per wave = bodies per block
 constexpr int kPS = kPW * kPL;     // bodies per super-block
+constexpr int kMaxDevices = 64;    // devices whose resident-workgroup counts are cached
 
 template <int K>
 struct PPath {
@@ -102,7 +111,9 @@ struct PairsGrid {
 // Three workgroups per CU fit the LDS; the register cap that lets them all be
 // resident costs the 8th-order FP64 kernel a few spilled bytes and is still
 // faster (609 against 637 us on the 16k disc) than two per CU.
-template <int K, Chain CH, bool QM>
+// SPLIT: workgroup b takes phase b % 4 of item b / 4 (and writes partials of
+// its own); otherwise workgroup b takes item b whole.
+template <int K, Chain CH, bool QM, bool SPLIT>
 __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const double *__restrict__ mass, PPath<K> path,
                                                           double G, double eps2, PairsGrid pg,
                                                           double *__restrict__ part, double *__restrict__ qpart)
@@ -116,12 +127,13 @@ __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const do
     __shared__ double wq[kPW];
     const int tid = threadIdx.x;
     const int w = tid / kPL, l = tid % kPL;
+    const int64_t item = SPLIT ? (int64_t)blockIdx.x / kPW : (int64_t)blockIdx.x;
     int I, J;   // super-blocks, relative to their chunks
     if (pg.tri) {
-        item_pair(blockIdx.x, pg.nsi, I, J);
+        item_pair(item, pg.nsi, I, J);
     } else {
-        I = (int)(blockIdx.x / pg.nsj);
-        J = (int)(blockIdx.x % pg.nsj);
+        I = (int)(item / pg.nsj);
+        J = (int)(item % pg.nsj);
     }
     const bool diag = pg.tri && I == J;
     I += pg.ci0;
@@ -161,7 +173,9 @@ __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const do
     __syncthreads();
 
     const int nphase = diag ? 3 : kPW;
-    for (int s = 0; s < nphase; ++s) {
+    const int s_lo = SPLIT ? (int)(blockIdx.x % kPW) : 0;
+    const int s_hi = SPLIT ? min(s_lo + 1, nphase) : nphase;
+    for (int s = s_lo; s < s_hi; ++s) {
         const int v = (w + s) % kPW;
         const bool same = diag && s == 0;                 // the wave's own block
         if (!(diag && s == 2 && w >= 2)) {                // wave-uniform
@@ -302,7 +316,7 @@ __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const do
         __syncthreads();
     }
 
-    // partials of this item: [2][NV][kPS], side 0 = super-block I, 1 = J
+    // partials of this workgroup: [2][NV][kPS], side 0 = super-block I, 1 = J
     double *pi = part + (int64_t)blockIdx.x * 2 * NV * kPS;
 #pragma unroll
     for (int k = 0; k <= K; ++k)
@@ -325,9 +339,25 @@ __global__ __launch_bounds__(kPS, 3) void force_pairs_kernel(int64_t n, const do
     }
 }
 
+// Partial of item k at p (one side and component): its workgroup's, or with
+// SPLIT the sum of its four phase workgroups' in phase order.
+template <bool SPLIT>
+__device__ __forceinline__ double item_part(const double *__restrict__ p, int64_t k, int64_t stride)
+{
+    if constexpr (!SPLIT) {
+        return p[k * stride];
+    } else {
+        double t = p[kPW * k * stride];
+#pragma unroll
+        for (int ph = 1; ph < kPW; ++ph) t += p[(kPW * k + ph) * stride];
+        return t;
+    }
+}
+
 // Every body's sums (one launch covering all of them, the triangle of the
 // single chunk): the i-side partials of the items (Kb, J), J = Kb..NS-1, then
 // the j-side partials of the items (I, Kb), I = 0..Kb, in that order.
+template <bool SPLIT>
 __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__restrict__ part,
                                     double *__restrict__ out)
 {
@@ -340,9 +370,10 @@ __global__ void reduce_pairs_kernel(int64_t n, int nv, int ns, const double *__r
     // (unrolled so that several loads are in flight; the additions keep their order)
     double s = 0.0;
 #pragma unroll 8
-    for (int J = kb; J < ns; ++J) s += part[item_index(kb, J, ns) * stride + (int64_t)comp * kPS + loc];
+    for (int J = kb; J < ns; ++J) s += item_part<SPLIT>(part + (int64_t)comp * kPS + loc, item_index(kb, J, ns), stride);
 #pragma unroll 8
-    for (int I = 0; I <= kb; ++I) s += part[item_index(I, kb, ns) * stride + (int64_t)(nv + comp) * kPS + loc];
+    for (int I = 0; I <= kb; ++I)
+        s += item_part<SPLIT>(part + (int64_t)(nv + comp) * kPS + loc, item_index(I, kb, ns), stride);
     out[e] = s;
 }
 
@@ -395,6 +426,27 @@ __global__ void zero_kernel(int64_t count, double *__restrict__ out)
     if (e < count) out[e] = 0.0;
 }
 
+// Workgroups of this kernel the current device holds at once (0 if the
+// query fails: then nothing is split); cached per device.
+template <int K, Chain CH, bool QM>
+int64_t resident_slots()
+{
+    static std::atomic<int> cache[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, force_pairs_kernel<K, CH, QM, true>, kPS, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        v = std::max(per_cu * cus, 0);
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 template <int K, Chain CH, bool QM>
 hipError_t launch_k(const ForceArgs &a, hipStream_t st)
 {
@@ -403,16 +455,30 @@ hipError_t launch_k(const ForceArgs &a, hipStream_t st)
     const int ns = (int)((a.n + kPS - 1) / kPS);
     const int nv = (K + 1) * 3;
     if (a.n <= kPairsMaxN) {
-        // one launch: the triangle of all super-blocks
+        // one launch: the triangle of all super-blocks, one workgroup per
+        // item and phase when the items are few and the workspace holds it
         const PairsGrid pg{0, ns, 0, ns, 1};
         const int64_t items = pairs_items(a.n);
-        hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM>), dim3((unsigned)items), dim3(kPS), 0, st, a.n, a.mass,
-                           path, a.G, a.eps2, pg, a.partial, a.qpart);
+        const bool split = pairs_split(items, resident_slots<K, CH, QM>()) &&
+                           kPW * items * 2 * nv * kPS <= a.partial_cap && (!QM || kPW * items <= a.qpart_cap);
+        const int64_t wgs = split ? kPW * items : items;
+        if (QM && a.q_count) *a.q_count = (int)wgs;
+        if (split)
+            hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM, true>), dim3((unsigned)wgs), dim3(kPS), 0, st, a.n,
+                               a.mass, path, a.G, a.eps2, pg, a.partial, a.qpart);
+        else
+            hipLaunchKernelGGL((force_pairs_kernel<K, CH, QM, false>), dim3((unsigned)wgs), dim3(kPS), 0, st, a.n,
+                               a.mass, path, a.G, a.eps2, pg, a.partial, a.qpart);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int64_t cnt = (int64_t)nv * a.n;
-        hipLaunchKernelGGL(reduce_pairs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n, nv, ns,
-                           (const double *)a.partial, a.out);
+        const dim3 rg((unsigned)((cnt + 255) / 256));
+        if (split)
+            hipLaunchKernelGGL(reduce_pairs_kernel<true>, rg, dim3(256), 0, st, a.n, nv, ns,
+                               (const double *)a.partial, a.out);
+        else
+            hipLaunchKernelGGL(reduce_pairs_kernel<false>, rg, dim3(256), 0, st, a.n, nv, ns,
+                               (const double *)a.partial, a.out);
         return hipGetLastError();
     }
     // chunks of cs super-blocks, as large as the workspace holds a rectangle
@@ -428,7 +494,7 @@ hipError_t launch_k(const ForceArgs &a, hipStream_t st)
         for (int B = A; B < nc; ++B) {
             PairsGrid pg{A * cs, min(cs, ns - A * cs), B * cs, min(cs, ns - B * cs), A == B ? 1 : 0};
             const int64_t items = pg.tri ? (int64_t)pg.nsi * (pg.nsi + 1) / 2 : (int64_t)pg.nsi * pg.nsj;
-            hipLaunchKernelGGL((force_pairs_kernel<K, CH, false>), dim3((unsigned)items), dim3(kPS), 0, st, a.n,
+            hipLaunchKernelGGL((force_pairs_kernel<K, CH, false, false>), dim3((unsigned)items), dim3(kPS), 0, st, a.n,
                                a.mass, path, a.G, a.eps2, pg, a.partial, (double *)nullptr);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -460,7 +526,26 @@ int64_t pairs_items(int64_t n)
     return ns * (ns + 1) / 2;
 }
 
-int64_t pairs_partial_doubles(int64_t n, int K) { return pairs_items(n) * 2 * (K + 1) * 3 * kPS; }
+bool pairs_split(int64_t items, int64_t slots) { return slots > 0 && 2 * items <= slots; }
+
+namespace {
+template <int K>
+int64_t max_slots()
+{
+    constexpr Chain kSplit = K == 1 ? Chain::Fp64 : Chain::Split;
+    return std::max({resident_slots<K, Chain::Fp64, false>(), resident_slots<K, Chain::Fp64, true>(),
+                     resident_slots<K, Chain::Mixed, false>(), resident_slots<K, Chain::Mixed, true>(),
+                     resident_slots<K, kSplit, false>(), resident_slots<K, kSplit, true>()});
+}
+}  // namespace
+
+int64_t pairs_partial_doubles(int64_t n, int K)
+{
+    const int64_t items = pairs_items(n);
+    const int64_t slots = K == 1 ? max_slots<1>() : K == 2 ? max_slots<2>() : max_slots<3>();
+    // split items take four workgroups each
+    return (pairs_split(items, slots) ? kPW * items : items) * 2 * (K + 1) * 3 * kPS;
+}
 
 int pairs_chunk(int64_t partial_cap, int K)
 {
@@ -476,15 +561,13 @@ hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st)
     if (a.k_first != 0 || a.K < 1 || a.K > 3) return hipErrorInvalidValue;
     const bool qm = a.qpart != nullptr;
     if (a.n <= kPairsMaxN) {
-        if (pairs_partial_doubles(a.n, a.K) > a.partial_cap) return hipErrorInvalidValue;
+        // the whole items must fit (split ones only where they fit too)
+        if (pairs_items(a.n) * 2 * (a.K + 1) * 3 * kPS > a.partial_cap) return hipErrorInvalidValue;
     } else {
         // chunked: no fused rate; chunks of at least 16 super-blocks
         if (qm || pairs_chunk(a.partial_cap, a.K) < kPairsMinChunk) return hipErrorInvalidValue;
     }
-    if (qm) {
-        if (pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
-        if (a.q_count) *a.q_count = (int)pairs_items(a.n);
-    }
+    if (qm && pairs_items(a.n) > a.qpart_cap) return hipErrorInvalidValue;
     switch (chain) {
         case Chain::Fp64: return qm ? launch_chain<Chain::Fp64, true>(a, st) : launch_chain<Chain::Fp64, false>(a, st);
         case Chain::Split:
