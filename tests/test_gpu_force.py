@@ -166,22 +166,31 @@ def test_force_derivs_pairs_once_largest(precision):
         assert within(deriv_error(g, o, mag, nat), TOL_MIXED)
 
 
+@pytest.mark.parametrize("n", [300, 9217])
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
-def test_pairs_once_masked_lanes_stay_finite(precision):
+def test_pairs_once_masked_lanes_stay_finite(precision, n):
     # Bodies 1e4 apart whose path adot is ~1e33: every real pair's chain fits
     # FP32 (it is scaled by 1/r^2 ~ 1e-8), but a lane that must drop its pair
     # (the second half of the diagonal block's step 32, or a padding body of
     # the ragged last super-block) would overflow FP32 at w = 1 and put
     # 0 * inf = NaN into real sums.  Such lanes take a zero path instead.
-    _say("pairs-once masked lanes %s" % precision)
-    n = 300                      # a full super-block and a ragged one
+    # n = 300: a full super-block and a ragged one, one workgroup per item
+    # and phase; n = 9217: one workgroup per item, a last super-block of one
+    # body (sampled i against the oracle).
+    _say("pairs-once masked lanes n=%d %s" % (n, precision))
     rng = np.random.default_rng(21)
     mass = rng.uniform(0.5, 1.5, n)
     path = [rng.uniform(-1e4, 1e4, (3, n)), rng.normal(size=(3, n)) * 1e3,
             rng.normal(size=(3, n)) * 1e10, rng.normal(size=(3, n)) * 1e33]
-    o, mag, nat = ho.pair_derivs(mass, path, K=3, with_mag=True, with_scale=True)
+    il = None
+    if n > 1000:
+        il = np.sort(rng.choice(n, 64, replace=False))
+        il[0], il[-1] = 0, n - 1
+    o, mag, nat = ho.pair_derivs(mass, path, K=3, i_list=il, with_mag=True, with_scale=True)
     g = _eval_gpu(8, mass, path, precision, launch=PAIRS)
     assert np.all(np.isfinite(g))
+    if il is not None:
+        g = g[:, :, il]
     assert _pairs_ok(g, o, mag, nat, precision)
 
 
@@ -204,6 +213,27 @@ def _kepler_path(w, K):
     path[2][:, 0] = 0.0
     path[3][:, 0] = 0.0
     return path[:K + 1]
+
+
+@pytest.mark.parametrize("order", [4, 8])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "split"])
+def test_force_derivs_pairs_once_whole_items_ragged(order, precision):
+    # Launches of few items take one workgroup per item and phase (every n
+    # the tests above use); from ~6900 bodies (~9000 at 4th order) on, one
+    # workgroup per item.  n = 9217: 703 items, whole on this GPU at every
+    # order, with a last super-block of one body.  Sampled i (the ragged
+    # block's body among them) against the oracle.
+    _say("pairs-once whole items n=9217 order=%d %s" % (order, precision))
+    n = 9217
+    p = order // 2 - 1
+    w = disc16k(n)
+    path = _kepler_path(w, p)
+    rng = np.random.default_rng(13)
+    il = np.sort(rng.choice(n, 96, replace=False))
+    il[0], il[-1] = 0, n - 1
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=p, i_list=il, with_mag=True, with_scale=True)
+    g = _eval_gpu(order, w["mass"], path, precision, launch=PAIRS)[:, :, il]
+    assert _pairs_ok(g, o, mag, nat, precision)
 
 
 @pytest.mark.parametrize("order,n", [(4, 32769), (8, 40000), (6, 50000)])
