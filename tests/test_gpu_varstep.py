@@ -192,16 +192,18 @@ def test_fused_rate_pairs_once(nb):
     assert rel_max(g["x"], o.x) <= 1e-13 and rel_max(g["v"], o.v) <= 1e-13
 
 
-def test_chunked_pairs_symmetric_step_matches_lds():
-    # beyond 32768 bodies the every-pair-once evaluation runs in chunks and
-    # keeps no rate, so the variable step takes the separate criterion pass;
-    # its steps must match those of the LDS kernel (which fuses the rate)
-    _say("symmetric step, chunked pairs vs LDS, n=33000")
-    n = 33000
+@pytest.mark.parametrize("order,n", [(4, 9217), (8, 9217), (4, 33000)])
+def test_pairs_symmetric_step_matches_lds(order, n):
+    # n = 9217: one every-pair-once launch of whole items (one workgroup per
+    # item at both orders) that carries the rate; n = 33000: beyond 32768
+    # bodies the evaluation runs in chunks and keeps no rate, so the variable
+    # step takes the separate criterion pass.  Either way the steps must
+    # match those of the LDS kernel (which fuses the rate).
+    _say("symmetric step, pairs vs LDS, order=%d n=%d" % (order, n))
     w, _ = disc_path(n, 1)
     out = {}
     for name, launch in (("lds", (2, 4, 0, 4)), ("pairs", (1, 0, 2, 4))):
-        h = Hermite(4, n, eps2=1e-10, device=DEV)
+        h = Hermite(order, n, eps2=1e-10, device=DEV)
         h.set_launch(*launch)
         st = h.state(w["mass"], w["x"], w["v"])
         h.init(st)
