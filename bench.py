@@ -550,6 +550,15 @@ def main():
         log("  %s: %.3e interactions/s, %.3f ms/step, eval %.3f ms, launch %s"
             % (prec, res[prec]["value"], res[prec]["ms_per_step"], res[prec]["eval_ms_avg"], res[prec]["launch"]))
     r, mx, sp = res["fp64"], res["mixed"], res["split"]
+    # the measured FMA issue ceiling (hermite_fma_rate), beside the published peak
+    from paper_2006_02501_amd import fma_rate
+    for rr, kind in ((r, "fp64"), (mx, "fp32")):
+        lane_fma = fma_rate(kind)
+        ceil = 2.0 * lane_fma / 1e12
+        rr["roofline"]["fma_loop"] = {"lane_fma_per_s": lane_fma, "tflops": ceil,
+                                      "frac": rr["roofline"]["achieved"] / ceil}
+        log("  %s FMA loop: %.3e lane-FMA/s = %.1f TFLOP/s; evaluation at %.2f of it"
+            % (kind, lane_fma, ceil, rr["roofline"]["achieved"] / ceil))
     de, dw = orbit_diffs(fin["fp64"], fin["mixed"])
     sde, sdw = orbit_diffs(fin["fp64"], fin["split"])
     out = {

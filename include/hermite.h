@@ -321,6 +321,18 @@ const char *hermite_last_error(const hermite_ctx *ctx);
 /* Library version string. */
 const char *hermite_version(void);
 
+/* Device probe (no context): the rate at which the current HIP device
+ * completes fused multiply-adds in the accumulating form d = a * b + d that
+ * the evaluation's chains use, in lane-FMA per second, in FP64 (precision
+ * HERMITE_FP64) or FP32 (HERMITE_MIXED).  Sixteen independent dependent
+ * chains per lane, 8192 workgroups of 256 lanes, 2048 iterations, the best
+ * of three launches timed with HIP events on a stream of its own (after a
+ * warm-up launch); it
+ * allocates and frees its own 8 or 16 MiB.  The evaluation's efficiency is
+ * quoted against this measured ceiling beside the published peak.  E_ARG for
+ * another precision or a NULL out, E_HIP if a HIP call fails. */
+hermite_status hermite_fma_rate(int32_t precision, double *lane_fma_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,6 +85,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_int32)]),
     "hermite_last_error": (ctypes.c_char_p, [_P]),
     "hermite_version": (ctypes.c_char_p, []),
+    "hermite_fma_rate": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -379,6 +380,16 @@ class EnsembleHermite:
         """(t, E) records of one system as a numpy array [count][2]."""
         r = self.rec[sys].cpu().numpy()
         return r if count is None else r[:count]
+
+
+def fma_rate(precision="fp64"):
+    """Measured FMA issue rate of the current device (lane-FMA/s) in the
+    accumulating form the evaluation's chains use: "fp64", or "fp32"
+    (hermite_fma_rate)."""
+    code = {"fp64": 0, "fp32": 1}[precision]   # HERMITE_FP64, HERMITE_MIXED
+    r = ctypes.c_double(0.0)
+    _check(None, load_library().hermite_fma_rate(code, ctypes.byref(r)))
+    return r.value
 
 
 def version():

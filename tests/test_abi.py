@@ -132,3 +132,12 @@ def test_batch_create_rejects_bad_order_and_null_offsets():
                                     None, ctypes.byref(ctx)) == -2
     p = Params(8, 0, 0, 0, 1.0, 0.0)
     assert lib.hermite_batch_create(ctypes.byref(p), 1, None, None, ctypes.byref(ctx)) == -1
+
+
+def test_fma_rate_rejects_bad_arguments():
+    # argument checks come before any HIP call (no GPU needed)
+    lib = load_library()
+    r = ctypes.c_double(0.0)
+    assert lib.hermite_fma_rate(2, ctypes.byref(r)) == -1
+    assert lib.hermite_fma_rate(-1, ctypes.byref(r)) == -1
+    assert lib.hermite_fma_rate(0, None) == -1
