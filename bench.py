@@ -33,14 +33,15 @@ FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
 # is reported only while their hash and the launch shape (which fixes the
 # split workspace) match what was profiled.
 KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/sym_kernels.hip",
-                  "paper_2006_02501_amd/csrc/pair_chain.h", "paper_2006_02501_amd/csrc/force_launch.h"]
+                  "paper_2006_02501_amd/csrc/pair_chain.h", "paper_2006_02501_amd/csrc/force_launch.h",
+                  "paper_2006_02501_amd/csrc/lane_moves.h"]
 # HBM bytes per evaluation (evaluation kernel and its reduction, plus the
 # j-record packing of the scalar source), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "ea3782404218808166ac860caf6e13c304e914acf5c67bc3422bf7ddf11eb6f1",
+        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -51,7 +52,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 118603947
     },
     "mixed": {
-        "sources_sha256": "ea3782404218808166ac860caf6e13c304e914acf5c67bc3422bf7ddf11eb6f1",
+        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -62,7 +63,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "ea3782404218808166ac860caf6e13c304e914acf5c67bc3422bf7ddf11eb6f1",
+        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,

@@ -14,6 +14,7 @@
 // a system stops correcting (and keeps its last iterate) after its own.
 #include "hermite_coeffs.h"
 #include "kernels.h"
+#include "lane_moves.h"
 #include "pair_chain.h"
 
 namespace hermite {
@@ -98,33 +99,6 @@ __global__ __launch_bounds__(kLanes) void batch_init_kernel(BatchPlan pl, int64_
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[((int64_t)(k - k_first) * 3 + c) * n + li.g] = acc[k][c];
     }
-}
-
-// Cross-lane moves of the j-side sums: one lane down the whole wave (DPP
-// rotate: lane l takes lane l + 1's value, lane 63 lane 0's), or from any
-// lane (ds_bpermute; addr = 4 x source lane).
-__device__ __forceinline__ double lane_down(double x)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ float lane_down(float x)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ double lane_from(int addr, double x)
-{
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ float lane_from(int addr, float x)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
 }
 
 // Bins whose largest system has at least this many bodies sweep the whole

@@ -41,6 +41,7 @@
 #include <type_traits>
 
 #include "force_launch.h"
+#include "lane_moves.h"
 #include "pair_chain.h"
 
 namespace hermite {
@@ -55,20 +56,6 @@ template <int K>
 struct PPath {
     const double *p[K + 1];
 };
-
-// The j-body's running sum moves one lane down: lane l receives lane l + 1's
-// value (lane 63 receives lane 0's).  Every lane of the wave must be active.
-__device__ __forceinline__ double lane_down(double x)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ float lane_down(float x)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xF, 0xF, false));
-}
 
 // First derivative order a chain sums in FP32 (K + 1: none).
 template <Chain CH, int K>
