@@ -105,8 +105,9 @@ __global__ __launch_bounds__(kLanes) void batch_init_kernel(BatchPlan pl, int64_
 // wave as one ring: 32 steps, sums moved by DPP.  The others sweep each system
 // as a ring of its own: largest/2 steps, sums moved by permutes, which go
 // through the LDS unit and make a step about a third dearer with two waves
-// per SIMD.  The measured break-even lies between 41 and 57 bodies.
-constexpr int kRingMin = 49;
+// per SIMD.  Measured on the 4096-system workload: 57 and 61 best, 49 ~1 %
+// and 41 ~5 % slower, no ring at all ~3 % (FP64) and ~10 % (mixed) slower.
+constexpr int kRingMin = 57;
 
 __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
 

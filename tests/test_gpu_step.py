@@ -274,15 +274,16 @@ def test_batch_matches_oracle(batch_workload, precision):
 def test_batch_sweep_kinds_match_oracle(batch_workload, precision):
     # Sizes chosen so that the packed bins take both sweeps of the batched
     # evaluation and their edge cases: whole-wave rings (a 64-body system
-    # alone, with its 32nd step from half the lanes; 50 + 14 and 49 + 15, the
-    # small system sitting at the end of the ring) and per-system rings
-    # (48 + 16 and 33 + 31, even sizes with a half last step; 7 + 3 + 2 + 1,
-    # including a two-body and a one-body system).
+    # alone, with its 32nd step from half the lanes; 58 + 6 and 57 + 7, the
+    # small system sitting at the end of the ring, 57 the smallest largest
+    # system that sweeps the whole wave) and per-system rings (56 + 8, 48 + 16
+    # and 33 + 31, even sizes with a half last step; 7 + 3 + 2 + 1, including
+    # a two-body and a one-body system).
     _say("batch sweep kinds %s" % precision)
     wb = batch_workload
     offs = wb["offsets"]
     sizes = np.diff(offs)
-    want = [64, 50, 14, 49, 15, 48, 16, 33, 31, 7, 3, 2, 1]
+    want = [64, 58, 6, 57, 7, 56, 8, 48, 16, 33, 31, 7, 3, 2, 1]
     mass, xs, vs, dts, parts = [], [], [], [], []
     for n in want:
         s = int(np.nonzero(sizes == max(n, 3))[0][0])
