@@ -211,9 +211,11 @@ hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, doubl
  * 1..64 particles).  Pair sums run only inside a system.  precision
  * HERMITE_SPLIT is not offered (E_ARG).  With params.compensated the state's
  * comp array is required and hermite_batch_init zeroes it.  All steps of all
- * systems run in one persistent kernel launch, replayed from a captured HIP
- * graph; systems are packed into 64-lane wavefronts and handed out longest
- * first from a device work counter.
+ * systems run in one persistent kernel launch (five one-wave workgroups per
+ * CU), replayed from a captured HIP graph; systems are packed into 64-lane
+ * wavefronts and handed out longest first from a device work counter.  An
+ * evaluation takes every pair of a system once, for both of its bodies (sums
+ * in another order than the single-system path, the same to rounding).
  */
 hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
                                     void *hip_stream, hermite_ctx **out);
