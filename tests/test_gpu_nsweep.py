@@ -110,3 +110,54 @@ def test_fig4_claims(sweep, order):
     assert worst[3] < 3.0 * worst[2] and worst[2] < 3.0 * worst[3], worst
     # n = 1 drifts secularly over the 2000 orbits
     assert late[0] > 3.0 * early[0], (early, late)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_per_system_iterations_in_both_sweeps(precision):
+    # Per-system counts in bins of both sweep kinds of the batched
+    # evaluation: a whole-wave ring (60 + 4 bodies) and per-system rings
+    # (40 + 24).  Pairs across systems count zero, so each system gets the
+    # bits of a run with its own n everywhere.
+    from workloads import batch_systems
+
+    _say("per-system n_iter in ring and segment bins %s" % precision)
+    wb = batch_systems()
+    sizes = np.diff(wb["offsets"])
+    want, counts = [60, 4, 40, 24], [3, 1, 4, 2]
+    mass, xs, vs, dts = [], [], [], []
+    for n in want:
+        s = int(np.nonzero(sizes == n)[0][0])
+        lo = wb["offsets"][s]
+        mass.append(wb["mass"][lo:lo + n])
+        xs.append(wb["x"][:, lo:lo + n])
+        vs.append(wb["v"][:, lo:lo + n])
+        dts.append(wb["dt"][s])
+    off = np.concatenate([[0], np.cumsum(want)]).astype(np.int64)
+    mass = np.concatenate(mass)
+    x = np.ascontiguousarray(np.concatenate(xs, axis=1))
+    v = np.ascontiguousarray(np.concatenate(vs, axis=1))
+    dts = np.array(dts)
+    steps = 12
+
+    def run(n_iter):
+        bh = BatchHermite(8, off, precision=precision, device=DEV)
+        st = bh.state(mass, x, v)
+        bh.init(st)
+        bh.run(st, dts, steps, n_iter)
+        d = st.host()
+        bh.close()
+        return d
+
+    mixed = run(counts)
+    for k, n in enumerate(counts):
+        uni = run(n)
+        sl = slice(off[k], off[k + 1])
+        assert np.array_equal(mixed["x"][:, sl], uni["x"][:, sl]), (want[k], n)
+        assert np.array_equal(mixed["v"][:, sl], uni["v"][:, sl]), (want[k], n)
+    if precision == "fp64":
+        # the ring bin's 60-body system against the oracle
+        o = ho.State(mass[:60], x[:, :60], v[:, :60], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, dts[0], 3)
+        assert rel_max(mixed["x"][:, :60], o.x) <= 1e-11 and rel_max(mixed["v"][:, :60], o.v) <= 1e-10
