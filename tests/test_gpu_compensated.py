@@ -258,3 +258,42 @@ def test_batched_compensation_lowers_round_off():
         worst[comp] = wst
     assert worst[False] < 1e-14
     assert worst[True] < 0.5 * worst[False], worst
+
+
+def test_batched_compensated_ring_bin_matches_oracle():
+    # compensated 8th-order batched kernel (one sweep step in flight, the
+    # iterate's x, v and compensation terms held in LDS between iterations)
+    # on a bin that sweeps the whole wave as one ring (60 + 4 bodies)
+    _say("batched compensated ring bin vs oracle")
+    from paper_2006_02501_amd import BatchHermite
+    from workloads import batch_systems
+
+    wb = batch_systems()
+    sizes = np.diff(wb["offsets"])
+    want = [60, 4]
+    mass, xs, vs, dts = [], [], [], []
+    for n in want:
+        s = int(np.nonzero(sizes == n)[0][0])
+        lo = wb["offsets"][s]
+        mass.append(wb["mass"][lo:lo + n])
+        xs.append(wb["x"][:, lo:lo + n])
+        vs.append(wb["v"][:, lo:lo + n])
+        dts.append(wb["dt"][s])
+    off = np.concatenate([[0], np.cumsum(want)]).astype(np.int64)
+    mass = np.concatenate(mass)
+    x = np.ascontiguousarray(np.concatenate(xs, axis=1))
+    v = np.ascontiguousarray(np.concatenate(vs, axis=1))
+    steps = 12
+    bh = BatchHermite(8, off, compensated=True, device=DEV)
+    st = bh.state(mass, x, v)
+    bh.init(st)
+    bh.run(st, np.array(dts), steps, 3)
+    g = st.host()
+    bh.close()
+    for k in range(len(want)):
+        sl = slice(off[k], off[k + 1])
+        o = ho.State(mass[sl], x[:, sl], v[:, sl], 3)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, dts[k], 3, compensated=True)
+        assert rel_max(g["x"][:, sl], o.x) <= 1e-11 and rel_max(g["v"][:, sl], o.v) <= 1e-10, want[k]
