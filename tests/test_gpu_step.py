@@ -317,6 +317,49 @@ def test_batch_sweep_kinds_match_oracle(batch_workload, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("order", [4, 6])
+def test_batch_sweep_kinds_lower_orders(batch_workload, order, precision):
+    # both sweep kinds of the batched evaluation at 4th and 6th order (one
+    # and two derivatives of the chain): rings 64 and 58 + 6, per-system
+    # rings 56 + 8
+    _say("batch sweep kinds order=%d %s" % (order, precision))
+    wb = batch_workload
+    offs = wb["offsets"]
+    sizes = np.diff(offs)
+    want = [64, 58, 6, 56, 8]
+    mass, xs, vs, dts = [], [], [], []
+    for n in want:
+        s = int(np.nonzero(sizes == n)[0][0])
+        lo = offs[s]
+        mass.append(wb["mass"][lo:lo + n])
+        xs.append(wb["x"][:, lo:lo + n])
+        vs.append(wb["v"][:, lo:lo + n])
+        dts.append(wb["dt"][s])
+    off = np.concatenate([[0], np.cumsum(want)]).astype(np.int64)
+    mass = np.concatenate(mass)
+    x = np.ascontiguousarray(np.concatenate(xs, axis=1))
+    v = np.ascontiguousarray(np.concatenate(vs, axis=1))
+    dts = np.array(dts)
+    p = order // 2 - 1
+    bh = BatchHermite(order, off, precision=precision, device=DEV)
+    st = bh.state(mass, x, v)
+    bh.init(st)
+    steps = 10
+    bh.run(st, dts, steps, 3)
+    d = st.host()
+    bh.close()
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    for k, n in enumerate(want):
+        lo, hi = off[k], off[k + 1]
+        o = ho.State(mass[lo:hi], x[:, lo:hi], v[:, lo:hi], p)
+        ho.init_derivs(o)
+        for _ in range(steps):
+            ho.step(o, dts[k], 3)
+        assert rel_max(d["x"][:, lo:hi], o.x) <= tol, n
+        assert rel_max(d["v"][:, lo:hi], o.v) <= tol * 10, n
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_full_size_sampled(batch_workload, precision):
     # all 4096 systems in one launch, as the benchmark runs them (default
     # persistent grid, graph capture); sampled systems against the oracle:
