@@ -211,11 +211,12 @@ hermite_status hermite_potential(hermite_ctx *ctx, const hermite_state *s, doubl
  * 1..64 particles).  Pair sums run only inside a system.  precision
  * HERMITE_SPLIT is not offered (E_ARG).  With params.compensated the state's
  * comp array is required and hermite_batch_init zeroes it.  All steps of all
- * systems run in one persistent kernel launch (five one-wave workgroups per
- * CU), replayed from a captured HIP graph; systems are packed into 64-lane
- * wavefronts and handed out longest first from a device work counter.  An
- * evaluation takes every pair of a system once, for both of its bodies (sums
- * in another order than the single-system path, the same to rounding).
+ * systems run in one persistent kernel launch (launch shape: see
+ * hermite_batch_set_launch), replayed from a captured HIP graph; systems are
+ * packed into 64-slot bins and handed out longest first from a device work
+ * counter.  An evaluation takes every pair of a system once, for both of its
+ * bodies (sums in another order than the single-system path, the same to
+ * rounding).
  */
 hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, const int64_t *offsets,
                                     void *hip_stream, hermite_ctx **out);
@@ -238,6 +239,48 @@ hermite_status hermite_batch_run(hermite_ctx *ctx, hermite_state *s, const doubl
  * n-sweep, Sec. 3.1, runs every n side by side this way). */
 hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const double *dt_sys,
                                        int32_t n_steps, const int32_t *n_iter_sys);
+
+/*
+ * Launch shape of the batched run.  All waves of a workgroup work on one bin
+ * of systems at a time; the workgroups are persistent and take bins from a
+ * device counter.
+ *   workgroups  persistent workgroups (0: as many as the GPU holds at once;
+ *               at most the bin count are launched)
+ *   waves       wave64 per workgroup, 1, 2 or 4: the waves split each
+ *               evaluation's sweep steps between them and the per-body work
+ *               (predictor, corrector) by coordinate component; their sums are
+ *               added through LDS in wave order
+ *   ring_min    bins whose largest system has at least ring_min bodies sweep
+ *               the whole wave as one ring, the j-side sums of a pair moving
+ *               between lanes by DPP; the others sweep each system as a ring
+ *               of its own, the sums moving by permutes (2..65; 65: never)
+ * Results are bitwise the same for every workgroup count (each bin is
+ * computed by one workgroup in a fixed order); waves and ring_min change the
+ * order of the sums, hence the rounding.  E_ARG for values outside these
+ * sets or a context that is not batched.  hermite_batch_get_launch reports
+ * the shape in use (the creation default: 2 waves for HERMITE_FP64, 4 for
+ * HERMITE_MIXED, ring_min 57, every resident workgroup).
+ *
+ * hermite_batch_autotune times every supported shape (waves 1, 2, 4;
+ * ring_min 57 or none; from half to all of the resident workgroups) for
+ * n_steps steps of n_iter iterations on a device copy of the given state (the
+ * state itself is not changed; the copy is allocated and freed inside the
+ * call, which synchronises), keeps the fastest and returns it through the
+ * non-NULL out pointers.  The pick is cached for the process (and, when the
+ * environment variable HERMITE_TUNE_CACHE names a file, in that file), keyed
+ * by order, precision, compensation, n_iter, the histogram of system sizes,
+ * the bin count and the device's architecture and CU count; a cached pick is
+ * returned without timing (*from_cache = 1).  hermite_autotune caches its
+ * picks the same way (keyed by order, precision, a quarter-octave bucket of n
+ * and the device).  hermite_tune_cache_clear forgets the cached picks of the
+ * process (not the file's).
+ */
+hermite_status hermite_batch_set_launch(hermite_ctx *ctx, int32_t workgroups, int32_t waves, int32_t ring_min);
+hermite_status hermite_batch_get_launch(hermite_ctx *ctx, int32_t *workgroups, int32_t *waves, int32_t *ring_min);
+hermite_status hermite_batch_autotune(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                      int32_t n_iter, int32_t *workgroups, int32_t *waves, int32_t *ring_min,
+                                      int32_t *from_cache);
+void hermite_tune_cache_clear(void);
 
 /*
  * Ensemble form (Sec. 3.3 N-body test, Table 1): n_sys independent systems of

@@ -2,14 +2,20 @@
 // advanced for many P(EC)^n steps in ONE persistent kernel launch.
 //
 // Systems are packed first-fit-decreasing into 64-lane bins on the host (one
-// lane per body).  Each workgroup is a single wave64; it takes the next bin
-// from a device counter (bins are ordered longest first), keeps every body's
-// state (x, v, a^(0..2p-1)) in VGPRs for all steps, and exchanges the
-// predicted / corrected path of the current iterate through LDS.  The only
-// global traffic per bin is the initial load, the final store and one counter
-// increment.  An evaluation takes each pair of a system once, for both of its
-// bodies, in a sweep over the bin's lanes (see the kernel); an idle lane, or a
-// lane without a pair in a sweep step, contributes zero.  Systems may take
+// lane slot per body).  Each workgroup holds W wave64 (W = 1, 2 or 4) that
+// work on one bin at a time, taken from a device counter (bins are ordered
+// longest first).  Every wave maps the bin's 64 slots onto its 64 lanes.
+// The per-body work of a step (predictor, corrector, interpolation) is split
+// by coordinate component: wave w keeps components w, w + W, ... of every
+// body of the bin in VGPRs for all steps, so with W = 4 each lane holds one
+// component of one body (wave 3 has none).  The O(N^2) evaluation is split by
+// sweep step: every wave takes a contiguous share of the bin's sweep steps
+// over the path of the current iterate, which sits in LDS.  The waves' sums
+// meet in LDS and are added in wave order, so the result does not depend on
+// timing.  The only global traffic per bin is the initial load, the final
+// store and one counter increment.  An evaluation takes each pair of a system
+// once, for both of its bodies (see the kernel); an idle lane, or a lane
+// without a pair in a sweep step, contributes zero.  Systems may take
 // different iteration counts n: a bin iterates as often as its largest n, and
 // a system stops correcting (and keeps its last iterate) after its own.
 #include "hermite_coeffs.h"
@@ -101,174 +107,194 @@ __global__ __launch_bounds__(kLanes) void batch_init_kernel(BatchPlan pl, int64_
     }
 }
 
-// Bins whose largest system has at least this many bodies sweep the whole
-// wave as one ring: 32 steps, sums moved by DPP.  The others sweep each system
-// as a ring of its own: largest/2 steps, sums moved by permutes, which go
-// through the LDS unit and make a step about a third dearer with two waves
-// per SIMD.  Measured on the 4096-system workload: 57 and 61 best, 49 ~1 %
-// and 41 ~5 % slower, no ring at all ~3 % (FP64) and ~10 % (mixed) slower.
-constexpr int kRingMin = 57;
 
 __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
 
 __device__ constexpr double kInvB[9] = {0.0, 1.0, 1.0 / 2.0, 1.0 / 3.0, 1.0 / 4.0, 1.0 / 5.0, 1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0};
 
-template <int P, bool MIXED, int CORR, bool COMP>
-__global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t n, const double *__restrict__ mass,
-                                                           double *__restrict__ pos, double *__restrict__ vel,
-                                                           double *__restrict__ deriv,
-                                                           const double *__restrict__ dt_sys, int n_steps,
-                                                           int n_iter, const int *__restrict__ iters, double G,
-                                                           double eps2, double *__restrict__ comp)
+// The row CX[corrector][P][0..P+1] of the position corrector in use (a kernel
+// argument, so one kernel serves every corrector).
+struct CorrRow {
+    double cx[kMaxP + 2];
+};
+
+template <int P, bool MIXED, bool COMP, int W>
+__global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
+    BatchPlan pl, int64_t n, const double *__restrict__ mass, double *__restrict__ pos, double *__restrict__ vel,
+    double *__restrict__ deriv, const double *__restrict__ dt_sys, int n_steps, int n_iter,
+    const int *__restrict__ iters, double G, double eps2, double *__restrict__ comp, CorrRow cr, int ring_min)
 {
     constexpr int K = P;
+    constexpr int NV = (K + 1) * 3;        // summed values per body: a^(0..K), 3 components each
+    constexpr int NC = (3 + W - 1) / W;    // coordinate components per lane in the per-body work
     // chain arithmetic: FP64, or FP32 from the FP64 differences (mixed)
     using T = typename std::conditional<MIXED, float, double>::type;
-    // two sweep steps in flight; the 8th-order FP64 kernel with compensation
+    // the lone-wave kernel keeps two sweep steps in flight (one wave alone on
+    // a SIMD is latency-bound); the 8th-order FP64 kernel with compensation
     // would exceed 256 registers with them
-    constexpr bool kTwoSteps = !(P == 3 && !MIXED && COMP);
-    __shared__ T sgm[kLanes];
-    __shared__ double sp[K + 1][3][kLanes];
-    __shared__ double wait_xv[COMP ? 12 : 1][kLanes];
+    constexpr bool kTwo = W == 1 && !(P == 3 && !MIXED && COMP);
+    __shared__ double sp[NV][kLanes];      // path of the current iterate: [3 k + c][slot]
+    __shared__ T sgm[kLanes];              // G m of every slot
+    __shared__ double part[W][NV][kLanes]; // each wave's sums over its sweep steps
     __shared__ int next_bin;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    // the wave index and every per-bin count below are the same in all lanes
+    // of a wave; saying so keeps the sweep and iteration loops scalar
+    const int w = __builtin_amdgcn_readfirstlane(tid / kLanes), l = tid % kLanes;
     const int64_t n3 = 3 * n;
 
     for (;;) {
-        if (lane == 0) next_bin = atomicAdd(pl.counter, 1);
+        if (tid == 0) next_bin = atomicAdd(pl.counter, 1);
         __syncthreads();
-        const int b = next_bin;
+        const int b = __builtin_amdgcn_readfirstlane(next_bin);
         __syncthreads();
         if (b >= pl.n_bins) break;
-        const LaneInfo li = lane_info(pl, b, lane, iters);
+        const LaneInfo li = lane_info(pl, b, l, iters);
         const bool active = li.sys >= 0;
-        // iterations of this bin and of this lane's system (the host checks
+        const int maxlen = __builtin_amdgcn_readfirstlane(li.maxlen);
+        // iterations of this bin and of this slot's system (the host checks
         // every count is in 1..64)
-        const int bin_iter = iters ? li.maxiter : n_iter;
+        const int bin_iter = iters ? __builtin_amdgcn_readfirstlane(li.maxiter) : n_iter;
         const int my_iter = (iters && active) ? iters[li.sys] : bin_iter;
 
-        double x[3], v[3], d[2 * P][3];
-        // Kahan compensation of x and v (COMP, the option of Sec. 3.2):
-        // the carried terms, and the ones the latest correction produced
-        double cx[3] = {0.0, 0.0, 0.0}, cv[3] = {0.0, 0.0, 0.0};
-        double ncx[3] = {0.0, 0.0, 0.0}, ncv[3] = {0.0, 0.0, 0.0};
+        // the components this lane keeps: c = w + ci W, ci < NC, c < 3
+        double x[NC], v[NC], d[2 * P][NC];
+        // Kahan compensation of x and v (COMP, the option of Sec. 3.2): the
+        // carried terms, and the ones the latest correction produced
+        double cx[NC], cv[NC], ncx[NC], ncv[NC];
         double dt = 1.0;
-        if (active) {
-            dt = dt_sys[li.sys];
+        if (active) dt = dt_sys[li.sys];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x[c] = pos[c * n + li.g];
-                v[c] = vel[c * n + li.g];
+        for (int ci = 0; ci < NC; ++ci) {
+            const int c = w + ci * W;
+            cx[ci] = cv[ci] = ncx[ci] = ncv[ci] = 0.0;
+            if (c < 3 && active) {
+                x[ci] = pos[c * n + li.g];
+                v[ci] = vel[c * n + li.g];
                 if constexpr (COMP) {
-                    cx[c] = comp[c * n + li.g];
-                    cv[c] = comp[n3 + c * n + li.g];
+                    cx[ci] = comp[c * n + li.g];
+                    cv[ci] = comp[n3 + c * n + li.g];
                 }
 #pragma unroll
-                for (int k = 0; k < 2 * P; ++k) d[k][c] = deriv[k * n3 + c * n + li.g];
-            }
-        } else {
+                for (int k = 0; k < 2 * P; ++k) d[k][ci] = deriv[k * n3 + c * n + li.g];
+            } else {
+                x[ci] = 1.0e3 * (l + 1);   // far from every real body; contributes nothing (mass 0)
+                v[ci] = 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x[c] = 1.0e3 * (lane + 1);   // far from every real body; contributes nothing (mass 0)
-                v[c] = 0.0;
-#pragma unroll
-                for (int k = 0; k < 2 * P; ++k) d[k][c] = 0.0;
+                for (int k = 0; k < 2 * P; ++k) d[k][ci] = 0.0;
             }
         }
-        const double gm = active ? G * mass[li.g] : 0.0;
-        const T gm_own = (T)gm;
-        sgm[lane] = gm_own;
+        if (w == 0) sgm[l] = (T)(active ? G * mass[li.g] : 0.0);
         // The bin's sweep (every pair of each system once, see below): its
-        // kind, its step count, the lane a segment sweep passes sums from, and
-        // the lane holding this body's j-side sums after the sweep.
-        const int sz = li.hi - li.lo, q = lane - li.lo, half = sz / 2;
-        const bool ring = li.maxlen >= kRingMin;
-        const int nsweep = ring ? min(li.maxlen - 1, kLanes / 2) : li.maxlen / 2;
+        // kind, its step count, this wave's share of the steps [t0, t1], and
+        // the lane a segment sweep passes sums from.
+        const int sz = li.hi - li.lo, q = l - li.lo, half = sz / 2;
+        const bool ring = maxlen >= ring_min;
+        const int nsweep = ring ? min(maxlen - 1, kLanes / 2) : maxlen / 2;
+        const int t0 = 1 + (w * nsweep) / W, t1 = ((w + 1) * nsweep) / W;
         const int succ = 4 * (li.lo + (q + 1 == sz ? 0 : q + 1));
-        int hq = q - nsweep % sz;
-        hq = hq < 0 ? hq + sz : hq;
-        const int home = 4 * (ring ? ((lane - nsweep) & (kLanes - 1)) : li.lo + hq);
 
         for (int step = 0; step < n_steps; ++step) {
-            // Taylor predictor from the t0 state (Horner form).
-            double path[K + 1][3];
+            // dt is redefined here for the compiler: without it, the
+            // predictor's, corrector's and interpolation's dt-derived factors
+            // are hoisted out of the step loop and held in registers through
+            // every sweep
+            asm volatile("" : "+v"(dt));
+            // Taylor predictor from the t0 state (Horner form) into the path.
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int ci = 0; ci < NC; ++ci) {
+                const int c = w + ci * W;
+                if (c >= 3) break;
                 double xs[2 * P + 2];
-                xs[0] = x[c];
-                xs[1] = v[c];
+                xs[0] = x[ci];
+                xs[1] = v[ci];
 #pragma unroll
-                for (int k = 0; k < 2 * P; ++k) xs[k + 2] = d[k][c];
+                for (int k = 0; k < 2 * P; ++k) xs[k + 2] = d[k][ci];
 #pragma unroll
                 for (int f = 0; f <= K; ++f) {
                     const int M = 2 * P + 1 - f;
                     double s = xs[f + M];
 #pragma unroll
                     for (int k = M - 1; k >= 0; --k) s = __builtin_fma(s, dt * kInvB[k + 1], xs[f + k]);
-                    path[f][c] = s;
+                    sp[3 * f + c][l] = s;
                 }
             }
-            double a1[K + 1][3];
-            double x1[3], v1[3];
+            double a1[K + 1][NC], x1[NC], v1[NC];
             for (int it = 0; it < bin_iter; ++it) {
-                __syncthreads();
+                // the start-of-step state is redefined here for the compiler,
+                // so that no product of it is hoisted out of the iteration
+                // loop and held in registers through the sweeps
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                for (int ci = 0; ci < NC; ++ci) {
+                    asm volatile("" : "+v"(x[ci]), "+v"(v[ci]));
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) sp[k][c][lane] = path[k][c];
-                __syncthreads();
-                // Evaluate a^(0..P) over the lane's own system, every pair
-                // once: the pair's chain adds to this lane's sums (the i-side)
-                // and, with the opposite sign and the other mass, to sums that
-                // travel with the partner (the j-side), passed one lane on
-                // between steps; after the sweep they go back to their body.
-                //  - ring: the whole wave is one ring; in step t = 1..nsweep
-                //    lane l takes lane l + t (mod 64) if it is of the same
-                //    system (at t = 32 only from lanes 0..31).  A system is
-                //    contiguous, so each of its pairs is at ring distance
+                    for (int k = 0; k <= P; ++k) asm volatile("" : "+v"(d[k][ci]));
+                }
+                __syncthreads();   // the iterate's path is in sp; part is free
+                // Evaluate a^(0..P) over each slot's own system, every pair
+                // once; this wave takes sweep steps t0..t1.  A pair's chain
+                // adds to the lane's own sums (the i-side) and, with the
+                // opposite sign and the other mass, to the partner's (the
+                // j-side).
+                //  - ring: the whole wave is one ring; in step t lane l takes
+                //    lane l + t (mod 64) if it is of the same system (at
+                //    t = 32 only from lanes 0..31).  A system is contiguous,
+                //    so each of its pairs is at ring distance
                 //    <= min(maxlen - 1, 32) one way round.
                 //  - segments: each system is a ring of its own; in step
                 //    t = 1..sz/2 local body q takes q + t (mod sz) (at t = sz/2
                 //    of an even sz only from its first half).
-                T acc[K + 1][3], accj[K + 1][3];
+                double xi[K + 1][3];
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
+                    for (int c = 0; c < 3; ++c) xi[k][c] = sp[3 * k + c][l];
+                const T gm_own = sgm[l];
+                T acc[K + 1][3];
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[k][c] = T(0);
+                // one pair of this lane's body with slot jc: the i-side into
+                // acc, the j-side into tj (no pair: zero differences, zero weight)
+                auto pair = [&](int jc, bool act, T(&tj)[K + 1][3]) {
+                    jc = act ? jc : l;
+                    T r[3], vv[3], aa[3], jj[3];
+#pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        acc[k][c] = T(0);
-                        accj[k][c] = T(0);
+                        r[c] = (T)(sp[c][jc] - xi[0][c]);
+                        vv[c] = (T)(sp[3 + c][jc] - xi[1][c]);
+                        aa[c] = K >= 2 ? (T)(sp[K >= 2 ? 6 + c : c][jc] - xi[K >= 2 ? 2 : 0][c]) : T(0);
+                        jj[c] = K >= 3 ? (T)(sp[K >= 3 ? 9 + c : c][jc] - xi[K >= 3 ? 3 : 0][c]) : T(0);
                     }
+                    T w2 = fma_t(r[0], r[0], fma_t(r[1], r[1], fma_t(r[2], r[2], (T)eps2)));
+                    w2 = act ? w2 : T(1);
+                    const T rinv = rsqrt_t(w2);
+                    const T rinv2 = rinv * rinv;
+                    const T q3 = act ? rinv * rinv2 : T(0);
+                    chain_pair<K, T>(r, vv, aa, jj, sgm[jc] * q3, -gm_own * q3, rinv2, acc, tj);
+                };
+                T accj[K + 1][3];
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) accj[k][c] = T(0);
                 // the sweep, RING a compile-time tag (one loop per kind)
                 auto sweep = [&](auto ring_tag) {
                     constexpr bool RING = decltype(ring_tag)::value;
-                    auto step = [&](int t) {
+                    auto step_t = [&](int t) {
                         int jc;
                         bool act;
                         if constexpr (RING) {
-                            const int pl = (lane + t) & (kLanes - 1);
-                            act = pl >= li.lo && pl < li.hi && !(t == kLanes / 2 && lane >= kLanes / 2);
-                            jc = pl;
+                            jc = (l + t) & (kLanes - 1);
+                            act = jc >= li.lo && jc < li.hi && !(t == kLanes / 2 && l >= kLanes / 2);
                         } else {
                             int q2 = q + t;
                             q2 = q2 >= sz ? q2 - sz : q2;
                             act = t <= half && !(2 * t == sz && q >= half);
                             jc = li.lo + q2;
                         }
-                        jc = act ? jc : lane;   // no pair: zero differences, zero weight
-                        T r[3], vv[3], aa[3], jj[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            r[c] = (T)(sp[0][c][jc] - path[0][c]);
-                            vv[c] = (T)(sp[1][c][jc] - path[1][c]);
-                            aa[c] = K >= 2 ? (T)(sp[K >= 2 ? 2 : 0][c][jc] - path[K >= 2 ? 2 : 0][c]) : T(0);
-                            jj[c] = K >= 3 ? (T)(sp[K >= 3 ? 3 : 0][c][jc] - path[K >= 3 ? 3 : 0][c]) : T(0);
-                        }
-                        T w = fma_t(r[0], r[0], fma_t(r[1], r[1], fma_t(r[2], r[2], (T)eps2)));
-                        w = act ? w : T(1);
-                        const T rinv = rsqrt_t(w);
-                        const T rinv2 = rinv * rinv;
-                        const T q3 = act ? rinv * rinv2 : T(0);
-                        chain_pair<K, T>(r, vv, aa, jj, sgm[jc] * q3, -gm_own * q3, rinv2, acc, accj);
+                        pair(jc, act, accj);
                     };
                     auto pass_on = [&]() {
 #pragma unroll
@@ -279,170 +305,173 @@ __global__ __launch_bounds__(kLanes) void batch_run_kernel(BatchPlan pl, int64_t
                                 else accj[k][c] = lane_from(succ, accj[k][c]);
                             }
                     };
-                    int t = 1;
-                    if (nsweep >= 1) {
-                        step(1);
-                        t = 2;
-                    }
-                    if constexpr (kTwoSteps) {
-                        for (; t + 1 <= nsweep; t += 2) {
-                            pass_on();
-                            step(t);
-                            pass_on();
-                            step(t + 1);
+                    if (t0 <= t1) {
+                        step_t(t0);
+                        int t = t0 + 1;
+                        if constexpr (kTwo) {
+                            for (; t + 1 <= t1; t += 2) {
+                                pass_on();
+                                step_t(t);
+                                pass_on();
+                                step_t(t + 1);
+                            }
                         }
-                    }
-                    for (; t <= nsweep; ++t) {
-                        pass_on();
-                        step(t);
+                        for (; t <= t1; ++t) {
+                            pass_on();
+                            step_t(t);
+                        }
                     }
                 };
                 if (ring) sweep(std::true_type{});
                 else sweep(std::false_type{});
-                // lane l now holds the j-side sums of body l + nsweep (ring) or
-                // of local body q + nsweep (segments)
+                // lane l now holds the j-side sums of slot h: l + t1 (ring)
+                // or local body q + t1 (segments); a wave without steps
+                // holds zeros
+                const int h = ring ? ((l + t1) & (kLanes - 1)) : li.lo + (q + t1) % sz;
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) accj[k][c] = lane_from(home, accj[k][c]);
+                    for (int c = 0; c < 3; ++c) part[w][3 * k + c][l] = (double)acc[k][c];
+                // (the wave's LDS operations complete in order: the
+                // additions below see the writes above)
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) part[w][3 * k + c][h] += (double)accj[k][c];
+                __syncthreads();   // every wave's sums are in part; sp may change
                 // a system past its own iteration count keeps its last iterate
                 if (it >= my_iter) continue;
+                // Modified corrector for this lane's components: velocity
+                // first, then position; the sums of the waves added in order.
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                for (int ci = 0; ci < NC; ++ci) {
+                    const int c = w + ci * W;
+                    if (c >= 3) break;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) a1[k][c] = (double)acc[k][c] + (double)accj[k][c];
-                // Modified corrector: velocity first, then position.
+                    for (int k = 0; k <= K; ++k) {
+                        double s = part[0][3 * k + c][l];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                        for (int u = 1; u < W; ++u) s += part[u][3 * k + c][l];
+                        a1[k][ci] = s;
+                    }
                     double dv = 0.0;
 #pragma unroll
                     for (int k = P; k >= 0; --k) {
-                        const double s = (k & 1) ? (a1[k][c] - d[k][c]) : (a1[k][c] + d[k][c]);
+                        const double s = (k & 1) ? (a1[k][ci] - d[k][ci]) : (a1[k][ci] + d[k][ci]);
                         dv = __builtin_fma(dv, dt, CV[P][k] * s);
                     }
                     if constexpr (COMP) {
-                        const double y = dv * dt - cv[c];
-                        v1[c] = v[c] + y;
-                        ncv[c] = (v1[c] - v[c]) - y;
+                        const double y = dv * dt - cv[ci];
+                        v1[ci] = v[ci] + y;
+                        ncv[ci] = (v1[ci] - v[ci]) - y;
                     } else {
-                        v1[c] = __builtin_fma(dv, dt, v[c]);
+                        v1[ci] = __builtin_fma(dv, dt, v[ci]);
                     }
                     double dx = 0.0;
 #pragma unroll
                     for (int k = P + 1; k >= 1; --k) {
-                        const double s = (k & 1) ? (a1[k - 1][c] - d[k - 1][c]) : (a1[k - 1][c] + d[k - 1][c]);
-                        dx = __builtin_fma(dx, dt, CX[CORR][P][k] * s);
+                        const double s = (k & 1) ? (a1[k - 1][ci] - d[k - 1][ci]) : (a1[k - 1][ci] + d[k - 1][ci]);
+                        dx = __builtin_fma(dx, dt, cr.cx[k] * s);
                     }
-                    dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1[c] + v[c]));
+                    dx = __builtin_fma(dx, dt, cr.cx[0] * (v1[ci] + v[ci]));
                     if constexpr (COMP) {
-                        const double y = dx * dt - cx[c];
-                        x1[c] = x[c] + y;
-                        ncx[c] = (x1[c] - x[c]) - y;
+                        const double y = dx * dt - cx[ci];
+                        x1[ci] = x[ci] + y;
+                        ncx[ci] = (x1[ci] - x[ci]) - y;
                     } else {
-                        x1[c] = __builtin_fma(dx, dt, x[c]);
+                        x1[ci] = __builtin_fma(dx, dt, x[ci]);
                     }
-                }
-                if (it + 1 < my_iter) {
+                    if (it + 1 < my_iter) {
+                        sp[c][l] = x1[ci];
+                        sp[3 + c][l] = v1[ci];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        path[0][c] = x1[c];
-                        path[1][c] = v1[c];
-#pragma unroll
-                        for (int m = 0; m <= K - 2; ++m) path[2 + m][c] = a1[m][c];
+                        for (int m = 0; m <= K - 2; ++m) sp[3 * (2 + m) + c][l] = a1[m][ci];
                     }
-                }
-                if constexpr (COMP) {
-                    // with compensation the iterate's x, v and their new
-                    // compensation terms wait in LDS (this lane's slots) over
-                    // later iterations: registers stay within 256
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        wait_xv[c][lane] = x1[c];
-                        wait_xv[3 + c][lane] = v1[c];
-                        wait_xv[6 + c][lane] = ncx[c];
-                        wait_xv[9 + c][lane] = ncv[c];
-                    }
-                }
-            }
-            if constexpr (COMP) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    x1[c] = wait_xv[c][lane];
-                    v1[c] = wait_xv[3 + c][lane];
-                    ncx[c] = wait_xv[6 + c][lane];
-                    ncv[c] = wait_xv[9 + c][lane];
                 }
             }
             // End of step: interpolated higher derivatives, then the new state.
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int ci = 0; ci < NC; ++ci) {
+                const int c = w + ci * W;
+                if (c >= 3) break;
                 if constexpr (P == 2) {
-                    const double num = I6_A0[0] * d[0][c] + I6_A1[0] * a1[0][c] +
-                                       (I6_A0[1] * d[1][c] + I6_A1[1] * a1[1][c]) * dt +
-                                       (I6_A0[2] * d[2][c] + I6_A1[2] * a1[2][c]) * (dt * dt);
-                    d[3][c] = num / (dt * dt * dt);
+                    const double num = I6_A0[0] * d[0][ci] + I6_A1[0] * a1[0][ci] +
+                                       (I6_A0[1] * d[1][ci] + I6_A1[1] * a1[1][ci]) * dt +
+                                       (I6_A0[2] * d[2][ci] + I6_A1[2] * a1[2][ci]) * (dt * dt);
+                    d[3][ci] = num / (dt * dt * dt);
                 }
                 if constexpr (P == 3) {
                     const double tp[4] = {1.0, dt, dt * dt, dt * dt * dt};
                     double n4 = 0.0, n5 = 0.0;
 #pragma unroll
                     for (int m = 0; m <= 3; ++m) {
-                        n4 += (I8_4_A0[m] * d[m][c] + I8_4_A1[m] * a1[m][c]) * tp[m];
-                        n5 += (I8_5_A0[m] * d[m][c] + I8_5_A1[m] * a1[m][c]) * tp[m];
+                        n4 += (I8_4_A0[m] * d[m][ci] + I8_4_A1[m] * a1[m][ci]) * tp[m];
+                        n5 += (I8_5_A0[m] * d[m][ci] + I8_5_A1[m] * a1[m][ci]) * tp[m];
                     }
-                    d[4][c] = n4 / (tp[3] * dt);
-                    d[5][c] = n5 / (tp[3] * tp[2]);
+                    d[4][ci] = n4 / (tp[3] * dt);
+                    d[5][ci] = n5 / (tp[3] * tp[2]);
                 }
 #pragma unroll
-                for (int k = 0; k <= P; ++k) d[k][c] = a1[k][c];
-                x[c] = x1[c];
-                v[c] = v1[c];
-                cx[c] = ncx[c];
-                cv[c] = ncv[c];
+                for (int k = 0; k <= P; ++k) d[k][ci] = a1[k][ci];
+                x[ci] = x1[ci];
+                v[ci] = v1[ci];
+                cx[ci] = ncx[ci];
+                cv[ci] = ncv[ci];
             }
         }
         if (active) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                pos[c * n + li.g] = x[c];
-                vel[c * n + li.g] = v[c];
+            for (int ci = 0; ci < NC; ++ci) {
+                const int c = w + ci * W;
+                if (c >= 3) break;
+                pos[c * n + li.g] = x[ci];
+                vel[c * n + li.g] = v[ci];
                 if constexpr (COMP) {
-                    comp[c * n + li.g] = cx[c];
-                    comp[n3 + c * n + li.g] = cv[c];
+                    comp[c * n + li.g] = cx[ci];
+                    comp[n3 + c * n + li.g] = cv[ci];
                 }
 #pragma unroll
-                for (int k = 0; k < 2 * P; ++k) deriv[k * n3 + c * n + li.g] = d[k][c];
+                for (int k = 0; k < 2 * P; ++k) deriv[k * n3 + c * n + li.g] = d[k][ci];
             }
         }
     }
 }
 
-template <int P, bool MIXED, bool COMP>
-hipError_t run_pmc(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
-                   double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
-                   double eps2, double *comp, int wg, hipStream_t st)
+template <int P, bool MIXED, bool COMP, int W>
+hipError_t run_w(const BatchPlan &pl, const CorrRow &cr, int64_t n, const double *mass, double *pos, double *vel,
+                 double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
+                 double eps2, double *comp, const BatchShape &sh, hipStream_t st)
 {
-    const dim3 g(wg), b(kLanes);
-    switch (corrector) {
-        case 0: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 0, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        case 1: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 1, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        case 2: hipLaunchKernelGGL((batch_run_kernel<P, MIXED, 2, COMP>), g, b, 0, st, pl, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp); break;
-        default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL((batch_run_kernel<P, MIXED, COMP, W>), dim3(sh.workgroups), dim3(kLanes * W), 0, st, pl, n,
+                       mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp, cr, sh.ring_min);
     return hipGetLastError();
 }
 
 // Compensation is a template switch so that the plain kernel carries no
 // compensation registers.
-template <int P, bool MIXED>
-hipError_t run_pm(const BatchPlan &pl, int corrector, int64_t n, const double *mass, double *pos, double *vel,
-                  double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
-                  double eps2, double *comp, int wg, hipStream_t st)
+template <int P, bool MIXED, bool COMP>
+hipError_t run_pmc(const BatchPlan &pl, const CorrRow &cr, int64_t n, const double *mass, double *pos, double *vel,
+                   double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
+                   double eps2, double *comp, const BatchShape &sh, hipStream_t st)
 {
-    return comp ? run_pmc<P, MIXED, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,
-                                          G, eps2, comp, wg, st)
-                : run_pmc<P, MIXED, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,
-                                           G, eps2, comp, wg, st);
+    switch (sh.waves) {
+        case 1: return run_w<P, MIXED, COMP, 1>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp, sh, st);
+        case 2: return run_w<P, MIXED, COMP, 2>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp, sh, st);
+        case 4: return run_w<P, MIXED, COMP, 4>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, comp, sh, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P, bool MIXED>
+hipError_t run_pm(const BatchPlan &pl, const CorrRow &cr, int64_t n, const double *mass, double *pos, double *vel,
+                  double *deriv, const double *dt_sys, int n_steps, int n_iter, const int *iters, double G,
+                  double eps2, double *comp, const BatchShape &sh, hipStream_t st)
+{
+    return comp ? run_pmc<P, MIXED, true>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2,
+                                          comp, sh, st)
+                : run_pmc<P, MIXED, false>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2,
+                                           comp, sh, st);
 }
 
 template <int K>
@@ -478,19 +507,65 @@ hipError_t launch_batch_init(const BatchPlan &pl, int p, int64_t n, const double
     return init_pass<5>(pl, n, mass, path, 4, G, eps2, deriv + 4 * n3, st);
 }
 
+namespace {
+template <int P, bool MIXED, bool COMP, int W>
+int resident_w()
+{
+    int per_cu = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_run_kernel<P, MIXED, COMP, W>, kLanes * W, 0);
+    return e == hipSuccess ? per_cu : 0;
+}
+
+template <int P, bool MIXED, bool COMP>
+int resident_pmc(const BatchShape &sh)
+{
+    switch (sh.waves) {
+        case 1: return resident_w<P, MIXED, COMP, 1>();
+        case 2: return resident_w<P, MIXED, COMP, 2>();
+        case 4: return resident_w<P, MIXED, COMP, 4>();
+        default: return 0;
+    }
+}
+
+template <int P>
+int resident_p(const BatchShape &sh, bool mixed, bool comp)
+{
+    if (mixed) return comp ? resident_pmc<P, true, true>(sh) : resident_pmc<P, true, false>(sh);
+    return comp ? resident_pmc<P, false, true>(sh) : resident_pmc<P, false, false>(sh);
+}
+}  // namespace
+
+int batch_resident_per_cu(const BatchShape &sh, int p, bool mixed, bool comp)
+{
+    switch (p) {
+        case 1: return resident_p<1>(sh, mixed, comp);
+        case 2: return resident_p<2>(sh, mixed, comp);
+        case 3: return resident_p<3>(sh, mixed, comp);
+        default: return 0;
+    }
+}
+
+bool batch_shape_ok(const BatchShape &sh)
+{
+    return sh.workgroups >= 1 && (sh.waves == 1 || sh.waves == 2 || sh.waves == 4) && sh.ring_min >= 2;
+}
+
 hipError_t launch_batch_run(const BatchPlan &pl, int p, bool mixed, int corrector, int64_t n, const double *mass,
                             double *pos, double *vel, double *deriv, const double *dt_sys, int n_steps, int n_iter,
-                            const int *iters, double G, double eps2, double *comp, int n_workgroups,
+                            const int *iters, double G, double eps2, double *comp, const BatchShape &shape,
                             hipStream_t st)
 {
     if (pl.n_bins <= 0 || n <= 0 || n_steps <= 0) return hipSuccess;
-    if (n_workgroups < 1) n_workgroups = 1;
+    if (!batch_shape_ok(shape) || corrector < 0 || corrector > 2 || p < 1 || p > 3) return hipErrorInvalidValue;
+    CorrRow cr{};
+    for (int k = 0; k <= p + 1; ++k) cr.cx[k] = CX[corrector][p][k];
 #define HERMITE_BATCH_CASE(PP)                                                                                     \
     case PP:                                                                                                       \
-        return mixed ? run_pm<PP, true>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,   \
-                                        G, eps2, comp, n_workgroups, st)                                                 \
-                     : run_pm<PP, false>(pl, corrector, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters,  \
-                                         G, eps2, comp, n_workgroups, st);
+        return mixed ? run_pm<PP, true>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G, eps2, \
+                                        comp, shape, st)                                                           \
+                     : run_pm<PP, false>(pl, cr, n, mass, pos, vel, deriv, dt_sys, n_steps, n_iter, iters, G,      \
+                                         eps2, comp, shape, st);
     switch (p) {
         HERMITE_BATCH_CASE(1)
         HERMITE_BATCH_CASE(2)

@@ -52,13 +52,27 @@ struct BatchPlan {
 hipError_t launch_batch_init(const BatchPlan &plan, int p, int64_t n, const double *mass, const double *pos,
                              const double *vel, double *deriv, double G, double eps2, hipStream_t st);
 
+// Launch shape of the batched run kernel.
+struct BatchShape {
+    int workgroups;   // persistent workgroups (>= 1; at most the bin count is useful)
+    int waves;        // wave64 per workgroup, all working on one bin: 1, 2 or 4
+    int ring_min;     // bins whose largest system has at least this many bodies
+                      // sweep the whole wave as one ring (> 64: never)
+};
+
+bool batch_shape_ok(const BatchShape &shape);
+
+// Workgroups of the batched run kernel of this shape (workgroups ignored) a
+// CU of the current device holds at once (0 if the query fails).
+int batch_resident_per_cu(const BatchShape &shape, int p, bool mixed, bool comp);
+
 // iters: per-system iteration counts (device, [n_sys], each 1..64) or null
 // for n_iter everywhere.
 // comp: [2][3][n] Kahan compensation of x and v, or null.
 hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int corrector, int64_t n,
                             const double *mass, double *pos, double *vel, double *deriv, const double *dt_sys,
                             int n_steps, int n_iter, const int *iters, double G, double eps2, double *comp,
-                            int n_workgroups, hipStream_t st);
+                            const BatchShape &shape, hipStream_t st);
 
 hipError_t launch_reset_counter(int *counter, hipStream_t st);
 

@@ -8,7 +8,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -54,21 +57,24 @@ struct hermite_ctx {
     bool ensemble = false;
     hermite::EnsembleCfg *d_cfg = nullptr;
     hermite::EnsembleStatus *d_status = nullptr;
-    int batch_workgroups = 0;
-    int batch_grid = 1280;   // default persistent grid (set at creation from the CU count)
+    int cus = 256;                                 // compute units of the device (batched form)
+    hermite::BatchShape bshape{1280, 1, 57};   // launch shape of the batched run (set at creation)
+    bool bshape_set = false;                       // fixed by hermite_batch_set_launch or the autotuner
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct Key {
         const double *mass, *dt;
         double *pos, *vel, *deriv, *comp;
-        int n_steps, n_iter, workgroups;
+        int n_steps, n_iter;
+        hermite::BatchShape shape;
         bool per_system;
         bool operator==(const Key &o) const
         {
             return mass == o.mass && dt == o.dt && pos == o.pos && vel == o.vel && deriv == o.deriv &&
-                   comp == o.comp && n_steps == o.n_steps && n_iter == o.n_iter && workgroups == o.workgroups &&
-                   per_system == o.per_system;
+                   comp == o.comp && n_steps == o.n_steps && n_iter == o.n_iter &&
+                   shape.workgroups == o.shape.workgroups && shape.waves == o.shape.waves &&
+                   shape.ring_min == o.shape.ring_min && per_system == o.per_system;
         }
     } key{};
 };
@@ -294,6 +300,116 @@ hermite_status eval_path(hermite_ctx *ctx, hermite_state *s, int *q_count)
     for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
     return run_force(ctx, s, eval_chain(ctx), p, 0, path, s->eval, ctx->ipt, ctx->nsplit, ctx->jsource, ctx->waves,
                      q_count);
+}
+
+// Launch-shape tuning cache: the autotuners' picks, keyed by what the best
+// shape depends on (the evaluation or the batched run, order, precision, the
+// problem size or the histogram of system sizes, the device's architecture
+// and CU count).  Kept for the life of the process; when the environment
+// variable HERMITE_TUNE_CACHE names a file, entries are also read from it at
+// first use and appended to it (one "key<TAB>values" line each).
+class TuneCache {
+public:
+    bool get(const std::string &key, std::vector<int> &val)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        load();
+        auto it = map_.find(key);
+        if (it == map_.end()) return false;
+        val = it->second;
+        return true;
+    }
+    void put(const std::string &key, const std::vector<int> &val)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        load();
+        map_[key] = val;
+        const char *path = std::getenv("HERMITE_TUNE_CACHE");
+        if (!path || !*path) return;
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s\t", key.c_str());
+            for (size_t i = 0; i < val.size(); ++i) std::fprintf(f, i ? " %d" : "%d", val[i]);
+            std::fprintf(f, "\n");
+            std::fclose(f);
+        }
+    }
+    void clear()
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        map_.clear();
+        loaded_ = true;   // a cleared cache does not re-read the file
+    }
+
+private:
+    void load()
+    {
+        if (loaded_) return;
+        loaded_ = true;
+        const char *path = std::getenv("HERMITE_TUNE_CACHE");
+        if (!path || !*path) return;
+        FILE *f = std::fopen(path, "r");
+        if (!f) return;
+        char line[1024];
+        while (std::fgets(line, sizeof line, f)) {
+            char *tab = std::strchr(line, '\t');
+            if (!tab) continue;
+            std::string key(line, tab);
+            std::vector<int> val;
+            char *p = tab + 1;
+            for (;;) {
+                char *end = nullptr;
+                const long x = std::strtol(p, &end, 10);
+                if (end == p) break;
+                val.push_back((int)x);
+                p = end;
+            }
+            if (!val.empty()) map_[key] = val;
+        }
+        std::fclose(f);
+    }
+    std::mutex mu_;
+    std::map<std::string, std::vector<int>> map_;
+    bool loaded_ = false;
+};
+
+TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+// Architecture name and CU count of the current device, for cache keys.
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        clear_hip_error();
+        return "unknown";
+    }
+    char buf[320];
+    std::snprintf(buf, sizeof buf, "%s:%d", prop.gcnArchName, prop.multiProcessorCount);
+    return buf;
+}
+
+// Workgroups of a batched shape that the device holds at once.
+int batch_resident(const hermite_ctx *ctx, const hermite::BatchShape &sh)
+{
+    const int per_cu = hermite::batch_resident_per_cu(sh, ctx->p, ctx->prm.precision == HERMITE_MIXED,
+                                                      ctx->prm.compensated != 0);
+    if (per_cu <= 0) clear_hip_error();
+    return std::max(1, per_cu) * ctx->cus;
+}
+
+// Default batched shape: two waves per bin for the FP64 chain, four for the
+// mixed one (whose smaller registers let three waves share a SIMD), the
+// whole-wave ring from 57 bodies, and as many persistent workgroups as the
+// GPU holds: the fastest shapes on the 4096-system workload.
+hermite::BatchShape default_batch_shape(const hermite_ctx *ctx)
+{
+    hermite::BatchShape sh{0, ctx->prm.precision == HERMITE_MIXED ? 4 : 2, 57};
+    sh.workgroups = batch_resident(ctx, sh);
+    return sh;
 }
 
 }  // namespace
@@ -578,7 +694,24 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
     };
     const Cand shapes[] = {{1, 4, 0}, {2, 4, 0}, {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {1, 16, 1}, {1, 4, 2}};
     int best_ipt = 1, best_split = 0, best_src = 1, best_waves = 4;
-    if (s->n > 0) {
+    // cache key: order, precision, the size bucket (a quarter octave of n) and the device
+    char key[384];
+    std::snprintf(key, sizeof key, "force|p=%d|prec=%d|nb=%d|dev=%s", ctx->p, ctx->prm.precision,
+                  s->n > 0 ? (int)std::floor(4.0 * std::log2((double)s->n)) : -1, device_tag().c_str());
+    std::vector<int> cached;
+    bool hit = false;
+    if (s->n > 0 && tune_cache().get(key, cached) && cached.size() == 4) {
+        // a cached shape is taken only if this context can run it
+        const bool pairs_ok = cached[2] != 2 || pairs_fit(ctx, s->n);
+        if (pairs_ok && hermite_set_launch(ctx, cached[0], cached[1], cached[2], cached[3]) == HERMITE_OK) {
+            best_ipt = cached[0];
+            best_split = cached[1];
+            best_src = cached[2];
+            best_waves = cached[3];
+            hit = true;
+        }
+    }
+    if (s->n > 0 && !hit) {
         // the events live until every return below; on failure the previous
         // launch shape is kept
         struct Events {
@@ -661,6 +794,7 @@ hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_p
             best_waves = pick->c.waves;
             best_src = pick->c.src;
             best_split = pick->split;
+            tune_cache().put(key, {best_ipt, best_split, best_src, best_waves});
         }
     }
     ctx->ipt = best_ipt;
@@ -729,7 +863,6 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
     ctx->offsets.assign(offsets, offsets + (n_sys + 1));
     ctx->n_max = n_sys > 0 ? offsets[n_sys] : 0;
     ctx->stream = (hipStream_t)hip_stream;
-    ctx->batch_workgroups = 0;
     auto alloc_copy = [&](void **dst, const void *src, size_t bytes) {
         if (bytes == 0) bytes = 8;
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -758,11 +891,6 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
         free_ctx(ctx);
         return HERMITE_E_HIP;
     }
-    // Persistent grid: five one-wave workgroups per CU.  Fewer than the two
-    // waves per SIMD the kernel's registers allow, so that most of the
-    // largest bins (handed out first, and setting the makespan) run alone on
-    // their SIMD, latency-bound but faster; measured on the 4096-system
-    // workload (2156 bins) with grids of 1024 to 3072 workgroups.
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -770,8 +898,9 @@ hermite_status hermite_batch_create(const hermite_params *prm, int32_t n_sys, co
             clear_hip_error();
             cus = 256;
         }
-        ctx->batch_grid = 5 * cus;
+        ctx->cus = cus;
     }
+    ctx->bshape = default_batch_shape(ctx);
     *out = ctx;
     return HERMITE_OK;
 }
@@ -836,11 +965,11 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
                 "per-system n_iter copy");
         HIP_TRY(ctx, hipEventRecord(ctx->iters_copied, ctx->stream), "per-system n_iter event");
     }
-    int wg = ctx->batch_workgroups;
-    if (wg <= 0) wg = std::min<int>(ctx->n_bins, ctx->batch_grid);
+    hermite::BatchShape sh = ctx->bshape;
+    sh.workgroups = std::max(1, std::min<int>(ctx->n_bins, sh.workgroups));
     const bool per_system = iters_host != nullptr;
     hermite_ctx::Key key{s->mass, dt_sys, s->pos, s->vel, s->deriv, comp_of(ctx, s), n_steps,
-                         per_system ? 0 : n_iter, wg, per_system};
+                         per_system ? 0 : n_iter, sh, per_system};
     if (!ctx->graph_exec || !(key == ctx->key)) {
         if (ctx->graph_exec) { (void)hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
         if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
@@ -850,7 +979,7 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
         hipError_t e2 = hermite::launch_batch_run(plan_of(ctx), ctx->p, ctx->prm.precision == HERMITE_MIXED,
                                                   ctx->prm.corrector, s->n, s->mass, s->pos, s->vel, s->deriv,
                                                   dt_sys, n_steps, n_iter, per_system ? ctx->d_iters : nullptr,
-                                                  ctx->prm.G, ctx->prm.eps2, comp_of(ctx, s), wg, cs);
+                                                  ctx->prm.G, ctx->prm.eps2, comp_of(ctx, s), sh, cs);
         hipGraph_t g = nullptr;
         hipError_t e3 = hipStreamEndCapture(cs, &g);
         if (e1 != hipSuccess) return hip_fail(ctx, e1, "graph capture (counter reset)");
@@ -867,6 +996,151 @@ static hermite_status batch_run_impl(hermite_ctx *ctx, hermite_state *s, const d
     const int64_t cnt[3] = {3 * s->n, 3 * s->n, (int64_t)2 * ctx->p * 3 * s->n};
     return check_finite(ctx, arrs, cnt, 3);
 }
+
+hermite_status hermite_batch_set_launch(hermite_ctx *ctx, int32_t workgroups, int32_t waves, int32_t ring_min)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
+    if (workgroups < 0) return fail(ctx, HERMITE_E_ARG, "hermite: workgroups must be >= 0");
+    if (waves != 1 && waves != 2 && waves != 4) return fail(ctx, HERMITE_E_ARG, "hermite: waves must be 1, 2 or 4");
+    if (ring_min < 2 || ring_min > 65) return fail(ctx, HERMITE_E_ARG, "hermite: ring_min must be in 2..65");
+    hermite::BatchShape sh{workgroups, waves, ring_min};
+    if (workgroups == 0) sh.workgroups = batch_resident(ctx, sh);
+    ctx->bshape = sh;
+    ctx->bshape_set = true;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_batch_get_launch(hermite_ctx *ctx, int32_t *workgroups, int32_t *waves, int32_t *ring_min)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
+    if (workgroups) *workgroups = std::max(1, std::min(ctx->n_bins, ctx->bshape.workgroups));
+    if (waves) *waves = ctx->bshape.waves;
+    if (ring_min) *ring_min = ctx->bshape.ring_min;
+    return HERMITE_OK;
+}
+
+hermite_status hermite_batch_autotune(hermite_ctx *ctx, hermite_state *s, const double *dt_sys, int32_t n_steps,
+                                      int32_t n_iter, int32_t *workgroups, int32_t *waves, int32_t *ring_min,
+                                      int32_t *from_cache)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (!ctx->batch) return fail(ctx, HERMITE_E_ARG, "hermite: not a batched context");
+    if (n_steps < 1) return fail(ctx, HERMITE_E_ARG, "hermite: n_steps must be >= 1");
+    if (n_iter < 1 || n_iter > 64) return fail(ctx, HERMITE_E_ARG, "hermite: n_iter must be in 1..64");
+    hermite_status st = check_state(ctx, s, true, false);
+    if (st != HERMITE_OK) return st;
+    if (s->n != ctx->n_max) return fail(ctx, HERMITE_E_ARG, "hermite: state n differs from the batch total");
+    if (ctx->n_sys > 0 && !dt_sys) return fail(ctx, HERMITE_E_ARG, "hermite: dt_sys is NULL");
+    auto report = [&](bool cached) {
+        (void)hermite_batch_get_launch(ctx, workgroups, waves, ring_min);
+        if (from_cache) *from_cache = cached ? 1 : 0;
+        return HERMITE_OK;
+    };
+    if (ctx->n_sys == 0) return report(false);
+    // cache key: order, precision, compensation, iterations, the histogram of
+    // system sizes (FNV-1a over the 64 counts), the bin count and the device
+    uint64_t hsh = 1469598103934665603ull;
+    {
+        int64_t hist[65] = {};
+        for (int32_t i = 0; i < ctx->n_sys; ++i) ++hist[ctx->offsets[i + 1] - ctx->offsets[i]];
+        for (int k = 1; k <= 64; ++k)
+            for (int b = 0; b < 8; ++b) {
+                hsh ^= (uint64_t)((hist[k] >> (8 * b)) & 0xff);
+                hsh *= 1099511628211ull;
+            }
+    }
+    char key[512];
+    std::snprintf(key, sizeof key, "batch|p=%d|prec=%d|comp=%d|n_iter=%d|sizes=%016llx|bins=%d|dev=%s", ctx->p,
+                  ctx->prm.precision, ctx->prm.compensated, n_iter, (unsigned long long)hsh, ctx->n_bins,
+                  device_tag().c_str());
+    std::vector<int> cached;
+    if (tune_cache().get(key, cached) && cached.size() == 3) {
+        const hermite::BatchShape sh{cached[0], cached[1], cached[2]};
+        if (hermite::batch_shape_ok(sh)) {
+            ctx->bshape = sh;
+            ctx->bshape_set = true;
+            return report(true);
+        }
+    }
+    // Time every candidate on a copy of the state (the caller's is left
+    // alone), each from the same starting point.
+    const int64_t n3 = 3 * s->n;
+    const size_t sbytes = (size_t)(2 + 2 * ctx->p) * n3 * sizeof(double);   // x, v, a^(0..2p-1)
+    const size_t cbytes = ctx->prm.compensated ? (size_t)2 * n3 * sizeof(double) : 0;
+    struct Scratch {
+        double *buf = nullptr;
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Scratch()
+        {
+            if (buf) (void)hipFree(buf);
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } sc;
+    if (hipMalloc((void **)&sc.buf, 2 * (sbytes + cbytes)) != hipSuccess) {
+        clear_hip_error();
+        return fail(ctx, HERMITE_E_ALLOC, "hermite: batched autotune could not allocate its state copy");
+    }
+    HIP_TRY(ctx, hipEventCreate(&sc.e[0]), "event create");
+    HIP_TRY(ctx, hipEventCreate(&sc.e[1]), "event create");
+    double *orig = sc.buf;                                   // pristine copy: x, v, deriv, comp
+    double *work = sc.buf + (sbytes + cbytes) / sizeof(double);
+    auto copy_state = [&](double *dst, const double *x, const double *v, const double *d, const double *c) {
+        hipError_t e = hipMemcpyAsync(dst, x, n3 * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst + n3, v, n3 * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst + 2 * n3, d, (size_t)2 * ctx->p * n3 * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream);
+        if (e == hipSuccess && cbytes)
+            e = hipMemcpyAsync(dst + sbytes / sizeof(double), c, cbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        return e;
+    };
+    HIP_TRY(ctx, copy_state(orig, s->pos, s->vel, s->deriv, comp_of(ctx, s)), "autotune state copy");
+    double *wx = work, *wv = work + n3, *wd = work + 2 * n3, *wc = cbytes ? work + sbytes / sizeof(double) : nullptr;
+    std::vector<hermite::BatchShape> cands;
+    for (int wv_ : {1, 2, 4})
+        for (int rm : {57, 65}) {
+            hermite::BatchShape sh{0, wv_, rm};
+            const int res = batch_resident(ctx, sh);
+            const int per_cu = std::max(1, res / std::max(1, ctx->cus));
+            // from half the resident workgroups to all of them, per CU
+            for (int k = std::max(1, per_cu / 2); k <= per_cu; ++k) {
+                sh.workgroups = std::min(ctx->n_bins, k * ctx->cus);
+                cands.push_back(sh);
+            }
+        }
+    hermite::BatchShape best = ctx->bshape;
+    float best_ms = 1e30f;
+    for (const hermite::BatchShape &sh : cands) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {   // a warm-up run, then the timed one
+            HIP_TRY(ctx, copy_state(work, orig, orig + n3, orig + 2 * n3, cbytes ? orig + sbytes / sizeof(double) : nullptr),
+                    "autotune state copy");
+            HIP_TRY(ctx, hipEventRecord(sc.e[0], ctx->stream), "event record");
+            HIP_TRY(ctx, hermite::launch_reset_counter(ctx->d_counter, ctx->stream), "autotune counter reset");
+            HIP_TRY(ctx, hermite::launch_batch_run(plan_of(ctx), ctx->p, ctx->prm.precision == HERMITE_MIXED,
+                                                   ctx->prm.corrector, s->n, s->mass, wx, wv, wd, dt_sys, n_steps,
+                                                   n_iter, nullptr, ctx->prm.G, ctx->prm.eps2, wc, sh, ctx->stream),
+                    "autotune batch launch");
+            HIP_TRY(ctx, hipEventRecord(sc.e[1], ctx->stream), "event record");
+            HIP_TRY(ctx, hipEventSynchronize(sc.e[1]), "event sync");
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, sc.e[0], sc.e[1]), "event time");
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    ctx->bshape = best;
+    ctx->bshape_set = true;
+    tune_cache().put(key, {best.workgroups, best.waves, best.ring_min});
+    return report(false);
+}
+
+void hermite_tune_cache_clear(void) { tune_cache().clear(); }
 
 static_assert(sizeof(hermite_vstep_cfg) == sizeof(hermite::EnsembleCfg), "cfg layout");
 static_assert(sizeof(hermite_vstep_result) == sizeof(hermite::EnsembleStatus), "result layout");

@@ -83,6 +83,11 @@ _SIGS = {
     "hermite_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "hermite_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hermite_batch_get_launch": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_int32)] * 3),
+    "hermite_batch_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]
+                               + [ctypes.POINTER(ctypes.c_int32)] * 4),
+    "hermite_tune_cache_clear": (None, []),
     "hermite_last_error": (ctypes.c_char_p, [_P]),
     "hermite_version": (ctypes.c_char_p, []),
     "hermite_fma_rate": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -306,6 +311,28 @@ class BatchHermite:
         self._dt = dt_sys          # keep alive: the captured graph holds its address
         return dt_sys
 
+    def set_launch(self, workgroups=0, waves=2, ring_min=57):
+        """Batched launch shape (hermite_batch_set_launch): persistent workgroups
+        (0: all resident), waves per bin (1, 2, 4), ring_min (whole-wave ring
+        from this many bodies; 65: never)."""
+        _check(self.ctx, self.lib.hermite_batch_set_launch(self.ctx, int(workgroups), int(waves), int(ring_min)))
+
+    def get_launch(self):
+        """The shape in use: (workgroups, waves, ring_min)."""
+        v = [ctypes.c_int32() for _ in range(3)]
+        _check(self.ctx, self.lib.hermite_batch_get_launch(self.ctx, *[ctypes.byref(q) for q in v]))
+        return tuple(q.value for q in v)
+
+    def autotune(self, st, dt_sys, n_steps, n_iter):
+        """Times the supported shapes on a copy of st (hermite_batch_autotune);
+        returns ((workgroups, waves, ring_min), from_cache)."""
+        dt_sys = self._dt_tensor(dt_sys)
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self.ctx, self.lib.hermite_batch_autotune(self.ctx, ctypes.byref(st.c),
+                                                         ctypes.c_void_p(dt_sys.data_ptr()), int(n_steps),
+                                                         int(n_iter), *[ctypes.byref(q) for q in v]))
+        return tuple(q.value for q in v[:3]), bool(v[3].value)
+
     def run(self, st, dt_sys, n_steps, n_iter):
         """n_iter: one count for every system, or a sequence of one per system."""
         dt_sys = self._dt_tensor(dt_sys)
@@ -390,6 +417,11 @@ def fma_rate(precision="fp64"):
     r = ctypes.c_double(0.0)
     _check(None, load_library().hermite_fma_rate(code, ctypes.byref(r)))
     return r.value
+
+
+def tune_cache_clear():
+    """Forget the autotuners' cached picks of this process (hermite_tune_cache_clear)."""
+    load_library().hermite_tune_cache_clear()
 
 
 def version():

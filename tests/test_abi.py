@@ -73,6 +73,10 @@ def test_null_context_calls():
     assert lib.hermite_step(None, ctypes.byref(s), 0.1, 3) == -1
     assert lib.hermite_batch_run(None, ctypes.byref(s), None, 1, 1) == -1
     assert lib.hermite_set_launch(None, 1, 1, 0, 4) == -1
+    assert lib.hermite_batch_set_launch(None, 0, 4, 57) == -1
+    assert lib.hermite_batch_get_launch(None, None, None, None) == -1
+    assert lib.hermite_batch_autotune(None, ctypes.byref(s), None, 1, 1, None, None, None, None) == -1
+    lib.hermite_tune_cache_clear()
     assert lib.hermite_destroy(None) == 0
     assert lib.hermite_last_error(None)
     assert b"gfx950" in lib.hermite_version()
