@@ -360,7 +360,31 @@ hermite_status hermite_set_launch(hermite_ctx *ctx, int32_t i_per_thread, int32_
 hermite_status hermite_autotune(hermite_ctx *ctx, hermite_state *s, int32_t *i_per_thread, int32_t *j_split,
                                 int32_t *j_source, int32_t *wg_waves);
 
-/* Message of the last failed call on ctx ("" if none; static string for NULL). */
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * evaluation of hermite_force_derivs (every pair once, as launch shape
+ * j_source 2 computes it) without a context: a^(0..p) along s->pred into
+ * s->eval, p = prm->order/2 - 1, for s->n bodies (s->mass, s->pred [p+1][3][n]
+ * and s->eval [p+1][3][n] device pointers; the other state fields are not
+ * used).  prm's order, precision, G and eps2 are used (validated as by
+ * hermite_create; E_ORDER / E_ARG), n in 0..2^40 (E_ARG beyond).
+ * Asynchronous on hip_stream (NULL = null stream).  It allocates nothing: the
+ * partial sums live in one 64 MiB device array per GPU, held from the first
+ * call on that GPU until the process ends.  One launch covers up to 13056
+ * bodies at 8th order (15104 at 6th, 18688 at 4th); more run as pairs of
+ * chunks sized to the array, whose results differ from hermite_force_derivs
+ * only by the rounding of the partial sums' order.  Calls on one GPU share
+ * the array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  On failure,
+ * hermite_last_error(NULL) gives the calling thread's message (E_HIP when
+ * the array's address cannot be found or the launch fails).
+ */
+hermite_status hermite_force_derivs_noalloc(const hermite_params *prm, hermite_state *s, void *hip_stream);
+
+/* Message of the last failed call on ctx ("" if none).  For NULL: the
+ * calling thread's last failure of hermite_force_derivs_noalloc, else a
+ * static string. */
 const char *hermite_last_error(const hermite_ctx *ctx);
 
 /* Library version string. */

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhermite.so")
 SOURCES = ["force_kernels.hip", "sym_kernels.hip", "step_kernels.hip", "timestep_kernels.hip", "batch_kernel.hip",
-           "ensemble_kernels.hip", "probe_kernels.hip", "runtime.cpp"]
+           "ensemble_kernels.hip", "probe_kernels.hip", "noalloc.hip", "runtime.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -36,6 +36,11 @@ struct ForceArgs {
     double *qpart = nullptr;
     int64_t qpart_cap = 0;
     int *q_count = nullptr;
+    // Every-pair-once evaluation of at most kPairsMaxN bodies whose single
+    // launch's partial sums exceed partial_cap: with this set it runs as
+    // pairs of chunks sized to the workspace (as beyond kPairsMaxN) instead
+    // of failing (no pair rate in that case).
+    bool chunks_if_needed = false;
 };
 
 // Launch shape of the FP64 / mixed evaluation (the generic initialisation

@@ -76,6 +76,10 @@ hipError_t launch_batch_run(const BatchPlan &plan, int p, bool mixed, int correc
 
 hipError_t launch_reset_counter(int *counter, hipStream_t st);
 
+// Message of the calling thread's last failed hermite_force_derivs_noalloc
+// ("" if none).
+const char *noalloc_message();
+
 // Ensemble form (systems of 2..128 bodies, one workgroup each, variable
 // time-symmetric steps on the device) -------------------------------------
 struct Path6Ptr {

@@ -418,7 +418,12 @@ extern "C" {
 
 const char *hermite_version(void) { return "paper_2006_02501_amd hermite 0.1 (gfx950)"; }
 
-const char *hermite_last_error(const hermite_ctx *ctx) { return ctx ? ctx->err.c_str() : kNoCtxMsg; }
+const char *hermite_last_error(const hermite_ctx *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    const char *m = hermite::noalloc_message();
+    return m && *m ? m : kNoCtxMsg;
+}
 
 hermite_status hermite_create(const hermite_params *prm, int64_t n_max, void *hip_stream, hermite_ctx **out)
 {

@@ -441,7 +441,7 @@ hipError_t launch_k(const ForceArgs &a, hipStream_t st)
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     const int ns = (int)((a.n + kPS - 1) / kPS);
     const int nv = (K + 1) * 3;
-    if (a.n <= kPairsMaxN) {
+    if (a.n <= kPairsMaxN && pairs_items(a.n) * 2 * nv * kPS <= a.partial_cap) {
         // one launch: the triangle of all super-blocks, one workgroup per
         // item and phase when the items are few and the workspace holds it
         const PairsGrid pg{0, ns, 0, ns, 1};
@@ -547,9 +547,10 @@ hipError_t launch_force_pairs(const ForceArgs &a, Chain chain, hipStream_t st)
     if (a.n <= 0) return hipSuccess;
     if (a.k_first != 0 || a.K < 1 || a.K > 3) return hipErrorInvalidValue;
     const bool qm = a.qpart != nullptr;
-    if (a.n <= kPairsMaxN) {
+    const bool single_fits = pairs_items(a.n) * 2 * (a.K + 1) * 3 * kPS <= a.partial_cap;
+    if (a.n <= kPairsMaxN && (single_fits || !a.chunks_if_needed)) {
         // the whole items must fit (split ones only where they fit too)
-        if (pairs_items(a.n) * 2 * (a.K + 1) * 3 * kPS > a.partial_cap) return hipErrorInvalidValue;
+        if (!single_fits) return hipErrorInvalidValue;
     } else {
         // chunked: no fused rate; chunks of at least 16 super-blocks
         if (qm || pairs_chunk(a.partial_cap, a.K) < kPairsMinChunk) return hipErrorInvalidValue;

@@ -88,6 +88,7 @@ _SIGS = {
     "hermite_batch_autotune": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P, ctypes.c_int32, ctypes.c_int32]
                                + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "hermite_tune_cache_clear": (None, []),
+    "hermite_force_derivs_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(StateC), _P]),
     "hermite_last_error": (ctypes.c_char_p, [_P]),
     "hermite_version": (ctypes.c_char_p, []),
     "hermite_fma_rate": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -417,6 +418,15 @@ def fma_rate(precision="fp64"):
     r = ctypes.c_double(0.0)
     _check(None, load_library().hermite_fma_rate(code, ctypes.byref(r)))
     return r.value
+
+
+def force_derivs_noalloc(order, st, precision="fp64", G=1.0, eps2=0.0, device="cuda:0"):
+    """One evaluation along st.pred into st.eval without a context and without
+    allocating (hermite_force_derivs_noalloc), on the current torch stream."""
+    lib = load_library()
+    prm = Params(int(order), PRECISIONS[precision], 0, 0, float(G), float(eps2), 0, 0)
+    _check(None, lib.hermite_force_derivs_noalloc(ctypes.byref(prm), ctypes.byref(st.c),
+                                                  _stream_handle(torch.device(device))))
 
 
 def tune_cache_clear():
