@@ -6,11 +6,17 @@ A timed step is one whole P(EC)^3 step -- predict, 3 x (evaluate a, adot,
 a^(2), a^(3); correct), interpolate -- with the state already in HBM.
 Metric: pair interactions per second, n_iter * N (N - 1) per step.  The
 top-level line is the FP64 path; the mixed-precision path is reported beside
-it, and so is the split path (FP64 a and adot, FP32 higher derivatives),
-each with its difference from the FP64 run.  The batched workload (4096 systems
-of 3..64 bodies, 1000 steps) is reported against one launch per system, and
-the disc again with the variable time-symmetric step of Sec. 3.3, and the
-2000-orbit iteration-count sweep of Sec. 3.1 (batched, n = 1..4 side by side).
+it, and so is the split path (FP64 a and adot, FP32 higher derivatives).
+Also timed by default, each in its own block: the batched workload (4096
+systems of 3..64 bodies, 1000 steps, autotuned launch shape) against one
+launch per system; the 64-body ring (10^4 steps of 4th order) and the
+e = 0.5 Kepler orbit (100 orbits) as batched launches of one system; the
+131,073-body Plummer cluster and the 1,048,576-body disc (one evaluation and
+whole steps, FP64 and mixed); the disc again with the variable
+time-symmetric step of Sec. 3.3; and the 2000-orbit iteration-count sweep of
+Sec. 3.1.  The cpu_baseline leg times the oracle on a sample of the disc and
+compares the FP64, mixed and split evaluations, and the orbital elements the
+three runs end with, against it.
 
 Prints ONE JSON line (N = 1 GPU only).
 """
@@ -41,44 +47,62 @@ KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_025
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
+        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 133997050,
-        "write_bytes": 118603947
+        "fetch_bytes": 134106425,
+        "write_bytes": 118403751
     },
     "mixed": {
-        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
+        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 124823478,
+        "fetch_bytes": 124696555,
         "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "d9a0642634d3c647bfdd503241285e9515c0847b0c73e86abb22c0a406d99fdd",
+        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
             "j_source": "pairs",
             "wg_waves": 4
         },
-        "fetch_bytes": 125085268,
+        "fetch_bytes": 124794602,
         "write_bytes": 103809024
     }
+}
+# j_source codes of hermite_set_launch: LDS tiles, scalar stream, every pair once
+# Executed work of the every-pair-once evaluation kernel per unordered pair,
+# from rocprofv3 --pmc runs of this benchmark (SQ_INSTS_VALU,
+# SQ_INSTS_VALU_FLOPS_FP64 and _FP32, each counting per wave instruction, so
+# times 64 lanes, over the N (N - 1) / 2 pairs of one 16k-disc evaluation);
+# reported only while the kernel sources and launch shape match.
+MEASURED_COUNTERS = {
+    "fp64": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+             "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
+             "valu_instr_per_pair": 126.6, "fp64_flops_per_pair": 158.2, "fp32_flops_per_pair": 0.0},
+    "mixed": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+              "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
+              "valu_instr_per_pair": 123.9, "fp64_flops_per_pair": 12.8, "fp32_flops_per_pair": 138.0},
+    "split": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+              "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
+              "valu_instr_per_pair": 141.7, "fp64_flops_per_pair": 68.5, "fp32_flops_per_pair": 91.0},
 }
 # j_source codes of hermite_set_launch: LDS tiles, scalar stream, every pair once
 JSOURCES = ["lds", "scalar", "pairs"]
 # MI355X published vector peaks: 256 CUs x 4 SIMD16 x 2 flops (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s FP64; FP32 twice that (157.3) with packed-FP32 issue.
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "split": 78.6}
+PAIRS_LAUNCH = (1, 0, 2, 4)   # every pair once: i_per_thread, j_split, j_source, wg_waves
 
 
 def eval_kernel_name(launch):
@@ -102,13 +126,39 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
+def _measured(table, precision, launch):
+    t = (table or {}).get(precision)
+    if not t or t["sources_sha256"] != kernel_sources_hash() or t["launch"] != launch:
+        return None
+    return t
+
+
 def measured_traffic(precision, launch):
     """Bytes per launch measured by the counter runs, or None when the kernel
     sources or the launch shape differ from what was profiled."""
-    t = (MEASURED_TRAFFIC or {}).get(precision)
-    if not t or t["sources_sha256"] != kernel_sources_hash() or t["launch"] != launch:
+    t = _measured(MEASURED_TRAFFIC, precision, launch)
+    return None if t is None else t["fetch_bytes"] + t["write_bytes"]
+
+
+def executed_work(precision, launch, n, eval_s, lane_fma_per_s):
+    """What the evaluation kernel executes (from the counter runs) at the
+    measured evaluation time, beside the algorithmic convention."""
+    t = _measured(MEASURED_COUNTERS, precision, launch)
+    if t is None:
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    pairs = n * (n - 1) / 2
+    f64 = t["fp64_flops_per_pair"] * pairs / eval_s / 1e12
+    f32 = t["fp32_flops_per_pair"] * pairs / eval_s / 1e12
+    lane_instr = t["valu_instr_per_pair"] * pairs / eval_s
+    return {"per_unordered_pair": {k: t[k] for k in ("valu_instr_per_pair", "fp64_flops_per_pair",
+                                                     "fp32_flops_per_pair")},
+            "fp64_tflops": f64, "fp32_tflops": f32,
+            "fp64_frac_of_peak": f64 / PEAK_TFLOPS["fp64"], "fp32_frac_of_peak": f32 / PEAK_TFLOPS["mixed"],
+            "valu_lane_instr_per_s": lane_instr,
+            "valu_issue_frac_of_fma_loop": lane_instr / lane_fma_per_s if lane_fma_per_s else None,
+            "note": "counted VALU instructions and flops of the kernel as run (every pair once), at the "
+                    "measured evaluation time; the convention figure above counts 144 flops per ordered "
+                    "pair, which the kernel does not execute"}
 
 
 def _energy(h, st):
@@ -119,6 +169,21 @@ def _energy(h, st):
     kin = 0.5 * torch.sum(m * torch.sum(st.vel * st.vel, dim=0))
     pot = 0.5 * torch.sum(m * phi)
     return float(kin + pot)
+
+
+def _system_energies(mass, x, v, offsets, G=1.0, eps2=0.0):
+    """Energy of every system of a batched state (host, FP64):
+    sum m v^2 / 2 - sum_{i<j} G m_i m_j (r_ij^2 + eps^2)^(-1/2)."""
+    out = np.empty(len(offsets) - 1)
+    for s in range(len(offsets) - 1):
+        lo, hi = offsets[s], offsets[s + 1]
+        m, xx, vv = mass[lo:hi], x[:, lo:hi], v[:, lo:hi]
+        kin = 0.5 * np.sum(m * np.sum(vv * vv, axis=0))
+        d = xx[:, :, None] - xx[:, None, :]
+        r = np.sqrt(np.sum(d * d, axis=0) + eps2)
+        iu = np.triu_indices(hi - lo, 1)
+        out[s] = kin - G * np.sum(m[iu[0]] * m[iu[1]] / r[iu])
+    return out
 
 
 def time_mode(precision, w, steps, warmup, autotune=True, launch=None):
@@ -183,6 +248,26 @@ def time_mode(precision, w, steps, warmup, autotune=True, launch=None):
     return res, final
 
 
+def gpu_evaluations(w, path, precisions=("fp64", "mixed", "split"), launch=PAIRS_LAUNCH):
+    """One evaluation of each chain along the given path (x, v, a, adot), in the
+    benchmark's launch shape; returns {precision: a^(0..3) [4][3][n]}."""
+    import torch
+    from paper_2006_02501_amd import Hermite
+
+    n = len(w["mass"])
+    out = {}
+    for prec in precisions:
+        h = Hermite(w["order"], n, precision=prec, G=w["G"], eps2=w["eps2"], device="cuda:0")
+        st = h.state(w["mass"], w["x"], w["v"])
+        h.set_launch(*launch)
+        for k, q in enumerate(path):
+            st.pred[k].copy_(torch.as_tensor(np.ascontiguousarray(q)))
+        h.force_derivs(st)
+        out[prec] = st.eval.cpu().numpy()
+        h.close()
+    return out
+
+
 def variable_step(w, steps, warmup, eta, launch):
     """The same disc with the implicit time-symmetric step of Sec. 3.3 (FP64,
     P(EC)^3, the FP64 launch shape): H_- at the start, H_+ at every
@@ -218,24 +303,18 @@ def variable_step(w, steps, warmup, eta, launch):
             "dt_first": dts[0], "dt_last": dts[-1]}
 
 
-def orbit_diffs(a, b, n_bodies=256):
-    """Eccentricity-vector and periapsis differences between two final states
-    for the first n_bodies stars relative to the central body."""
-    from oracle import hermite_oracle as ho
-
-    de, dw = 0.0, 0.0
-    for k in range(1, n_bodies + 1):
-        ea, _, wa = ho.kepler_elements(a["mass"], a["x"], a["v"], k)
-        eb, _, wb = ho.kepler_elements(b["mass"], b["x"], b["v"], k)
-        de = max(de, float(np.sqrt(((ea - eb) ** 2).sum())))
-        dw = max(dw, abs(ho.wrap_angle(wa - wb)))
-    return de, dw
+def _stats(a):
+    a = np.asarray(a, dtype=np.float64)
+    return {"median": float(np.median(a)), "p99": float(np.quantile(a, 0.99)), "max": float(a.max())}
 
 
-def cpu_baseline(w, target_s=12.0):
+def cpu_baseline(w, gpu_eval, finals, target_s=12.0):
     """The oracle (plain FP64 C, OpenMP over i) on a bounded sample of the same
     workload: i-particles against all N j-particles, 8th-order derivatives,
-    repeated until about target_s seconds of CPU work."""
+    repeated until about target_s seconds of CPU work.  On the same sample it
+    also states the error of the GPU evaluations against the oracle (gpu_eval:
+    a function of the path returning each chain's a^(0..3)), and the orbital
+    elements of the stars after the FP64, mixed and split runs (finals)."""
     from oracle import hermite_oracle as ho
 
     n = len(w["mass"])
@@ -259,14 +338,57 @@ def cpu_baseline(w, target_s=12.0):
         total += time.perf_counter() - t0
         reps += 1
     rate = reps * m_i * (n - 1) / total
-    return dict(value=rate, unit="pair interactions/s", cores=ho.num_threads(), kind="oracle",
+    base = dict(value=rate, unit="pair interactions/s", cores=ho.num_threads(), kind="oracle",
                 sample="%d x (%d random i-particles x all %d j-particles), 8th-order derivatives, %.1f s"
                        % (reps, m_i, n, total))
+    # Accuracy on the same i: per derivative order, the plain relative error
+    # |g - o| / |o| of each particle's vector (median, p99, max), and the
+    # measure of the parity bars, max |g - o|_inf / max(|o|, 0.1 S[, N]) with
+    # S the sum of pair-term magnitudes and N the natural derivative scale
+    # (mixed and split).
+    o, mag, nat = ho.pair_derivs(w["mass"], path, K=3, i_list=il, with_mag=True, with_scale=True)
+    g_all = gpu_eval(path)
+    u32 = 2.0 ** -24
+    bars = {"fp64": [1e-12] * 4, "mixed": [max(1e-6, u32 * m) for m in (1.0, 4.0, 34.0, 466.0)]}
+    bars["split"] = [1e-12, 1e-12] + bars["mixed"][2:]
+    acc_out = {"sample": "the same %d i-particles, path x, v and the oracle's a, adot" % m_i}
+    for prec, g in g_all.items():
+        g = g[:, :, il]
+        per = {}
+        for k in range(4):
+            on = np.sqrt((o[k] * o[k]).sum(axis=0))
+            rel = np.sqrt(((g[k] - o[k]) ** 2).sum(axis=0)) / np.where(on > 0, on, 1.0)
+            den = np.maximum(on, 0.1 * mag[k])
+            if prec != "fp64":
+                den = np.maximum(den, nat[k])
+            bar = np.abs(g[k] - o[k]).max(axis=0) / np.where(den > 0, den, 1.0)
+            per["a%d" % k] = dict(_stats(rel), bar_measure_max=float(bar.max()), bar=bars[prec][k])
+        acc_out[prec] = per
+    # Orbital elements after the runs (Appendix A, first equation: e; Sec. 3.1:
+    # omega), stars against the central body: differences of mixed and split
+    # from FP64; omega only for e > 0.02, where it is well conditioned, and
+    # e * |d omega| (the rotation of the periapsis direction) for all.
+    orb = {}
+    k_max = min(256, n - 1)
+    el = {p: [ho.kepler_elements(f["mass"], f["x"], f["v"], k) for k in range(1, k_max + 1)]
+          for p, f in finals.items()}
+    for prec in ("mixed", "split"):
+        if prec not in el or "fp64" not in el:
+            continue
+        de = [float(np.sqrt(((a[0] - b[0]) ** 2).sum())) for a, b in zip(el[prec], el["fp64"])]
+        dw = [abs(ho.wrap_angle(a[2] - b[2])) for a, b in zip(el[prec], el["fp64"])]
+        ew = [b[1] * d for b, d in zip(el["fp64"], dw)]
+        well = [d for b, d in zip(el["fp64"], dw) if b[1] > 0.02]
+        orb[prec] = {"bodies_compared": k_max, "max_ecc_vector_diff": max(de),
+                     "max_periapsis_diff_rad_e_gt_0.02": max(well) if well else None,
+                     "bodies_e_gt_0.02": len(well), "max_e_times_periapsis_diff": max(ew)}
+    return base, acc_out, orb
 
 
-def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
+def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True, tune_steps=20, autotune=True):
     """4096 systems of 3..64 bodies, 8th order, P(EC)^3, per-system dt, in one
-    persistent graph-captured launch; against hermite_step on each system."""
+    persistent graph-captured launch, its shape picked by the autotuner (or
+    the default shape); against hermite_step on each system."""
     import torch
     from paper_2006_02501_amd import BatchHermite, Hermite
     from workloads import batch_systems
@@ -279,13 +401,23 @@ def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
     out = {"n_systems": int(len(sizes)), "bodies": int(offs[-1]), "steps": steps, "n_iter": n_iter,
            "interactions_per_eval": inter_eval}
     dt = torch.as_tensor(wb["dt"]).to("cuda:0")
+    E0 = _system_energies(wb["mass"], wb["x"], wb["v"], offs)
+    flops = FLOPS_PER_INTERACTION[8] * inter_eval * n_iter * steps
     for prec in ("fp64", "mixed"):
         bh = BatchHermite(8, offs, precision=prec, device="cuda:0")
         st = bh.state(wb["mass"], wb["x"], wb["v"])
         bh.init(st)
+        default_shape = bh.get_launch()
+        t0 = time.perf_counter()
+        shape, cached = bh.autotune(st, dt, tune_steps, n_iter) if autotune else (default_shape, False)
+        tune_s = time.perf_counter() - t0 if autotune else None
         bh.run(st, dt, steps, n_iter)          # graph capture + warm-up
         torch.cuda.synchronize()
-        bh.init(st)                            # same buffers: the captured graph is replayed
+        # back to the initial state in the same buffers (the captured graph is
+        # replayed on them)
+        st.pos.copy_(torch.as_tensor(wb["x"]))
+        st.vel.copy_(torch.as_tensor(wb["v"]))
+        bh.init(st)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -293,14 +425,36 @@ def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        d = st.host()
         bh.close()
-        out[prec] = {"ms": ms, "interactions_per_s": steps * n_iter * inter_eval / (ms / 1e3)}
+        dE = np.abs(_system_energies(d["mass"], d["x"], d["v"], offs) / E0 - 1.0)
+        achieved = flops / (ms / 1e3) / 1e12
+        out[prec] = {"ms": ms, "interactions_per_s": steps * n_iter * inter_eval / (ms / 1e3),
+                     "launch": {"workgroups": shape[0], "waves_per_bin": shape[1], "ring_min": shape[2]},
+                     "default_launch": {"workgroups": default_shape[0], "waves_per_bin": default_shape[1],
+                                        "ring_min": default_shape[2]},
+                     "autotune_s": tune_s, "autotune_from_cache": cached,
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
+                                  "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec]},
+                     "energy_rel_change_per_system": dict(
+                         _stats(dE), systems_above_1e_6=int(np.sum(dE > 1e-6)),
+                         note="systems above 1e-6 are the most tightly packed ones (Hill spacing ~2-3), "
+                              "whose planets meet at separations down to ~1e-4 that the fixed step "
+                              "P_inner/500 cannot resolve; the oracle shows the same jumps on them")}
     if not per_system:
         return out
-    # one launch sequence per system (hermite_step), a sample, extrapolated
+    # one launch sequence per system (hermite_step), a sample, extrapolated;
+    # the same systems after the same steps of a batched run, compared
     pick = np.linspace(0, len(sizes) - 1, baseline_systems).astype(int)
+    bh = BatchHermite(8, offs, device="cuda:0")
+    bst = bh.state(wb["mass"], wb["x"], wb["v"])
+    bh.init(bst)
+    bh.run(bst, dt, baseline_steps + 1, n_iter)
+    bd = bst.host()
+    bh.close()
     t_total = 0.0
     inter_sample = 0
+    worst = 0.0
     for s in pick:
         lo, hi = offs[s], offs[s + 1]
         h = Hermite(8, hi - lo, device="cuda:0")
@@ -314,13 +468,90 @@ def batched(steps, baseline_systems=64, baseline_steps=10, per_system=True):
         torch.cuda.synchronize()
         t_total += time.perf_counter() - t0
         inter_sample += baseline_steps * n_iter * int((hi - lo) * (hi - lo - 1))
+        g = st.host()
+        for key in ("x", "v"):
+            scale = np.abs(g[key]).max()
+            worst = max(worst, float(np.abs(bd[key][:, lo:hi] - g[key]).max() / (scale if scale > 0 else 1.0)))
         h.close()
     rate = inter_sample / t_total
     out["per_system_launches"] = {"interactions_per_s": rate,
                                   "sample": "%d systems x %d steps, hermite_step per system, extrapolated"
                                             % (baseline_systems, baseline_steps),
-                                  "extrapolated_ms": steps * n_iter * inter_eval / rate * 1e3}
+                                  "extrapolated_ms": steps * n_iter * inter_eval / rate * 1e3,
+                                  "max_rel_diff_from_batched_fp64": worst}
     out["speedup_fp64_vs_per_system"] = out["fp64"]["interactions_per_s"] / rate
+    return out
+
+
+def _ecc_omega(mass, x, v):
+    """Eccentricity vector (the Laplace-Runge-Lenz vector over mu) and its angle
+    in the xy-plane for body 1 about body 0 (the planar Kepler orbit)."""
+    mu = mass[0] + mass[1]
+    r = x[:, 1] - x[:, 0]
+    u = v[:, 1] - v[:, 0]
+    e = ((u @ u - mu / np.sqrt(r @ r)) * r - (r @ u) * u) / mu
+    return e, float(np.arctan2(e[1], e[0]))
+
+
+def small_systems():
+    """The 64-body ring (4th order, n = 2, dt = 2 pi / 1000, 10 orbits = 10^4
+    steps) and the e = 0.5 Kepler orbit (same scheme, 100 orbits), each as a
+    batched launch of one system: the whole run is one persistent kernel,
+    replayed from a captured graph; beside it the same steps through
+    hermite_step, one launch sequence per step."""
+    import torch
+    from paper_2006_02501_amd import BatchHermite, Hermite
+    from workloads import kepler_two_body, ring64
+
+    out = {}
+    wr = ring64()
+    wk = kepler_two_body(e=0.5)
+    for name, w, steps in (("ring64", wr, wr["steps"]),
+                           ("kepler_e0.5", dict(wk, n_iter=2, dt=2 * np.pi / 1000),
+                            int(round(100 * wk["period"] / (2 * np.pi / 1000))))):
+        n = len(w["mass"])
+        off = np.array([0, n], dtype=np.int64)
+        bh = BatchHermite(4, off, device="cuda:0")
+        st = bh.state(w["mass"], w["x"], w["v"])
+        bh.init(st)
+        dt = torch.full((1,), w["dt"], dtype=torch.float64, device="cuda:0")
+        bh.run(st, dt, steps, w["n_iter"])     # capture + warm-up
+        st.pos.copy_(torch.as_tensor(w["x"]))
+        st.vel.copy_(torch.as_tensor(w["v"]))
+        bh.init(st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bh.run(st, dt, steps, w["n_iter"])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        d = st.host()
+        bh.close()
+        E0 = _system_energies(w["mass"], w["x"], w["v"], off)[0]
+        E1 = _system_energies(d["mass"], d["x"], d["v"], off)[0]
+        inter = steps * w["n_iter"] * n * (n - 1)
+        res = {"bodies": n, "order": 4, "n_iter": w["n_iter"], "dt": w["dt"], "steps": steps,
+               "batched_one_system_ms": ms, "us_per_step": ms * 1e3 / steps,
+               "interactions_per_s": inter / (ms / 1e3), "energy_rel_change": E1 / E0 - 1.0}
+        if n == 2:
+            ea, wa = _ecc_omega(w["mass"], w["x"], w["v"])
+            eb, wb_ = _ecc_omega(d["mass"], d["x"], d["v"])
+            res["ecc_change"] = float(np.sqrt(eb @ eb) - np.sqrt(ea @ ea))
+            res["periapsis_change_rad"] = float(np.angle(np.exp(1j * (wb_ - wa))))
+        # the same scheme through hermite_step (launch sequences), 200 steps
+        h = Hermite(4, n, device="cuda:0")
+        hs = h.state(w["mass"], w["x"], w["v"])
+        h.init(hs)
+        h.step(hs, w["dt"], w["n_iter"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            h.step(hs, w["dt"], w["n_iter"])
+        torch.cuda.synchronize()
+        res["hermite_step_us_per_step"] = (time.perf_counter() - t0) / 200 * 1e6
+        h.close()
+        out[name] = res
     return out
 
 
@@ -419,21 +650,23 @@ def table1(chunk=200000, etas=(0.08, 0.04, 0.02, 0.01, 0.005), iters=(3, 4), t_e
 
 
 def other_configs():
-    """The cluster (131,073 bodies, 6th order, eps = 1e-4, dt = 1/4096, P(EC)^2,
-    10 steps; autotuned) and the large disc (1,048,576 bodies, 8th order: one
-    evaluation and one P(EC)^3 step; every pair once, the shape the autotuner
-    picks on the 16k disc and on the cluster, since timing every candidate at
-    this size would take minutes), in FP64 and mixed precision."""
+    """The cluster (131,073 bodies, 6th order, eps = 1e-4, dt = 1/4096, P(EC)^2:
+    evaluations and 10 steps; autotuned launch shape) and the large disc
+    (1,048,576 bodies, 8th order: one evaluation and one P(EC)^3 step; every
+    pair once, the shape the autotuner picks on the 16k disc and on the
+    cluster, since timing every candidate at this size would take minutes),
+    in FP64 and mixed precision; evaluations timed with events on the
+    library's stream."""
     import torch
     from paper_2006_02501_amd import Hermite
     from workloads import large_disc, plummer_cluster
 
     out = {}
-    fixed = {"fp64": (1, 0, 2, 4), "mixed": (1, 0, 2, 4)}
-    for name, w, steps, eval_reps in (("plummer_cluster", plummer_cluster(), 10, 3), ("large_disc", large_disc(), 1, 1)):
+    for name, wfun, steps, eval_reps in (("plummer_cluster", plummer_cluster, 10, 3), ("large_disc", large_disc, 1, 1)):
+        w = wfun()
         n = len(w["mass"])
         order, n_iter, dt = w["order"], w["n_iter"], w["dt"]
-        res = {"n_bodies": n, "order": order, "n_iter": n_iter, "dt": dt, "steps": steps}
+        res = {"n_bodies": n, "order": order, "n_iter": n_iter, "dt": dt, "steps": steps, "eps2": w["eps2"]}
         for prec in ("fp64", "mixed"):
             h = Hermite(order, n, precision=prec, G=w["G"], eps2=w["eps2"], device="cuda:0")
             st = h.state(w["mass"], w["x"], w["v"])
@@ -447,16 +680,19 @@ def other_configs():
                 log("    %s %s: autotune ..." % (name, prec))
                 shape = h.autotune(st)
             else:
-                shape = fixed[prec]
+                shape = PAIRS_LAUNCH
                 h.set_launch(*shape)
             log("    %s %s: timing ..." % (name, prec))
             E0 = _energy(h, st)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(eval_reps):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(eval_reps)]
+            for a, b in ev:
+                a.record()
                 h.force_derivs(st)
+                b.record()
             torch.cuda.synchronize()
-            t_eval = (time.perf_counter() - t0) / eval_reps
+            t_eval = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
             t0 = time.perf_counter()
             for _ in range(steps):
                 h.step(st, dt, n_iter)
@@ -465,14 +701,16 @@ def other_configs():
             E1 = _energy(h, st)
             h.close()
             inter = n * (n - 1)
+            tflops = FLOPS_PER_INTERACTION[order] * inter / t_eval / 1e12
             res[prec] = {"launch": list(shape), "init_s": t_init, "eval_ms": t_eval * 1e3,
                          "eval_interactions_per_s": inter / t_eval,
-                         "eval_tflops": FLOPS_PER_INTERACTION[order] * inter / t_eval / 1e12,
+                         "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_TFLOPS[prec],
+                                      "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS[prec]},
                          "ms_per_step": t_steps / steps * 1e3,
                          "step_interactions_per_s": steps * n_iter * inter / t_steps,
                          "energy_rel_change": (E1 - E0) / abs(E0)}
-            log("    %s %s: eval %.2f ms (%.3e interactions/s), step %.2f ms" % (name, prec, t_eval * 1e3,
-                                                                               inter / t_eval, t_steps / steps * 1e3))
+            log("    %s %s: eval %.2f ms (%.3e interactions/s, %.2f of peak), step %.2f ms"
+                % (name, prec, t_eval * 1e3, inter / t_eval, tflops / PEAK_TFLOPS[prec], t_steps / steps * 1e3))
         out[name] = res
     return out
 
@@ -502,12 +740,13 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-variable-step", action="store_true")
     ap.add_argument("--no-fig4", action="store_true", help="skip the 2000-orbit iteration-count sweep")
+    ap.add_argument("--no-small-systems", action="store_true", help="skip the 64-body ring and the Kepler orbit")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the 131k cluster and the 1M-body disc (about a minute)")
     ap.add_argument("--table1", action="store_true",
                     help="also run the Sec. 3.3 N-body test grid (Table 1) to t = 100 pi (a few minutes)")
     ap.add_argument("--table1-only", action="store_true", help="run only the Table 1 grid")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
-    ap.add_argument("--other-configs", action="store_true",
-                    help="also time the 131k cluster and the 1M-body disc (about a minute)")
     ap.add_argument("--table1-etas", default="0.08,0.04,0.02,0.01,0.005")
     ap.add_argument("--table1-iters", default="3,4", help="iteration counts of the 8th-order rows")
     ap.add_argument("--eta", type=float, default=0.4,
@@ -531,7 +770,8 @@ def main():
         print(json.dumps({"table1": table1(etas=etas, iters=iters)}), flush=True)
         return
     if args.batched_only:
-        print(json.dumps({"batched": batched(args.batched_steps, per_system=not args.no_per_system)}), flush=True)
+        print(json.dumps({"batched": batched(args.batched_steps, per_system=not args.no_per_system,
+                                             autotune=not args.no_autotune)}), flush=True)
         return
 
     calib = calibrate_copy() if args.calibrate_copy else None
@@ -551,17 +791,23 @@ def main():
         log("  %s: %.3e interactions/s, %.3f ms/step, eval %.3f ms, launch %s"
             % (prec, res[prec]["value"], res[prec]["ms_per_step"], res[prec]["eval_ms_avg"], res[prec]["launch"]))
     r, mx, sp = res["fp64"], res["mixed"], res["split"]
-    # the measured FMA issue ceiling (hermite_fma_rate), beside the published peak
+    # the measured FMA issue ceiling (hermite_fma_rate), beside the published
+    # peak, and what the kernel executes (counter figures) at its measured time
     from paper_2006_02501_amd import fma_rate
+    lane_fma = {}
     for rr, kind in ((r, "fp64"), (mx, "fp32")):
-        lane_fma = fma_rate(kind)
-        ceil = 2.0 * lane_fma / 1e12
-        rr["roofline"]["fma_loop"] = {"lane_fma_per_s": lane_fma, "tflops": ceil,
-                                      "frac": rr["roofline"]["achieved"] / ceil}
-        log("  %s FMA loop: %.3e lane-FMA/s = %.1f TFLOP/s; evaluation at %.2f of it"
-            % (kind, lane_fma, ceil, rr["roofline"]["achieved"] / ceil))
-    de, dw = orbit_diffs(fin["fp64"], fin["mixed"])
-    sde, sdw = orbit_diffs(fin["fp64"], fin["split"])
+        lane_fma[kind] = fma_rate(kind)
+        ceil = 2.0 * lane_fma[kind] / 1e12
+        rr["roofline"]["fma_loop"] = {"lane_fma_per_s": lane_fma[kind], "tflops": ceil,
+                                      "frac": rr["roofline"]["achieved"] / ceil,
+                                      "note": "convention flops (144 per ordered pair) over the measured "
+                                              "FMA-loop rate; the kernel executes fewer (see executed)"}
+        log("  %s FMA loop: %.3e lane-FMA/s = %.1f TFLOP/s; evaluation at %.2f of it (convention)"
+            % (kind, lane_fma[kind], ceil, rr["roofline"]["achieved"] / ceil))
+    for prec, rr in res.items():
+        ex = executed_work(prec, rr["launch"], n, rr["eval_ms_avg"] / 1e3,
+                           lane_fma["fp64" if prec == "fp64" else "fp32"])
+        rr["roofline"]["executed"] = ex
     out = {
         "metric": "pair interactions/sec for 8th-order derivs at N=16k: mixed vs FP64, 1 GPU",
         "value": r["value"],
@@ -585,14 +831,11 @@ def main():
         "fp64": {k: v for k, v in r.items() if k != "roofline"},
         "mixed": dict(mx, dtype="f32 chain, f64 state/differences/cross-tile sums",
                       vs_fp64={"energy_rel_change_diff": mx["energy_rel_change"] - r["energy_rel_change"],
-                               "max_ecc_vector_diff": de, "max_periapsis_diff_rad": dw,
-                               "bodies_compared": 256, "after_steps": args.steps + args.warmup}),
+                               "after_steps": args.steps + args.warmup}),
         "mixed_over_fp64": mx["value"] / r["value"],
-        "split": dict({k: v for k, v in sp.items() if k != "roofline"},
-                      dtype="f64 a and adot, f32 a^(2) and a^(3) chain",
+        "split": dict(sp, dtype="f64 a and adot, f32 a^(2) and a^(3) chain",
                       vs_fp64={"energy_rel_change_diff": sp["energy_rel_change"] - r["energy_rel_change"],
-                               "max_ecc_vector_diff": sde, "max_periapsis_diff_rad": sdw,
-                               "bodies_compared": 256, "after_steps": args.steps + args.warmup}),
+                               "after_steps": args.steps + args.warmup}),
         "split_over_fp64": sp["value"] / r["value"],
     }
     if calib:
@@ -606,15 +849,19 @@ def main():
         out["variable_step"] = vs
         log("  variable step: %.3f ms/step (x%.3f of the fixed step), criterion %.3f ms"
             % (vs["ms_per_step"], vs["over_fixed_step_ms"], vs["criterion_ms_with_copy"]))
+    if not args.no_small_systems:
+        log("  ring64 and Kepler ...")
+        out["small_systems"] = small_systems()
+        log("  small systems: %s" % json.dumps({k: v["us_per_step"] for k, v in out["small_systems"].items()}))
     if not args.no_fig4:
         log("  fig4 n-sweep ...")
         out["fig4_nsweep"] = fig4_sweep()
         log("  fig4 n-sweep: %s" % json.dumps({k: v for k, v in out["fig4_nsweep"].items() if k.startswith("order")}))
     if not args.no_batched:
         log("  batched ...")
-        out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system)
-        log("  batched: %s" % json.dumps({k: out["batched"][k] for k in ("fp64", "mixed")}))
-    if args.other_configs:
+        out["batched"] = batched(args.batched_steps, per_system=not args.no_per_system, autotune=not args.no_autotune)
+        log("  batched: %s" % json.dumps({k: out["batched"][k]["ms"] for k in ("fp64", "mixed")}))
+    if not args.no_other_configs:
         log("  cluster and large disc ...")
         out["other_configs"] = other_configs()
     if args.table1:
@@ -623,7 +870,15 @@ def main():
                                iters=tuple(int(q) for q in args.table1_iters.split(",")))
     if not args.no_cpu_baseline:
         log("  cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w)
+        base, acc, orb = cpu_baseline(w, lambda path: gpu_evaluations(w, path), fin)
+        out["cpu_baseline"] = base
+        for prec in ("fp64", "mixed", "split"):
+            out[prec]["vs_oracle"] = acc[prec]
+            out[prec]["vs_oracle"]["sample"] = acc["sample"]
+        for prec in ("mixed", "split"):
+            out[prec]["vs_fp64"].update(orb.get(prec, {}))
+        out["fp64"]["vs_oracle"]["whole_steps"] = ("x, v within 1e-13 of the oracle after one step and 1e-10 "
+                                                   "after 100 (tests/test_gpu_step.py)")
     print(json.dumps(out), flush=True)
 
 

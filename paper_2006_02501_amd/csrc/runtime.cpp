@@ -404,10 +404,12 @@ int batch_resident(const hermite_ctx *ctx, const hermite::BatchShape &sh)
 // Default batched shape: two waves per bin for the FP64 chain, four for the
 // mixed one (whose smaller registers let three waves share a SIMD), the
 // whole-wave ring from 57 bodies, and as many persistent workgroups as the
-// GPU holds: the fastest shapes on the 4096-system workload.
+// GPU holds: the fastest shapes on the 4096-system workload.  Systems of at
+// most 16 bodies take at most 8 sweep steps, too few to share: one wave.
 hermite::BatchShape default_batch_shape(const hermite_ctx *ctx)
 {
-    hermite::BatchShape sh{0, ctx->prm.precision == HERMITE_MIXED ? 4 : 2, 57};
+    const int waves = ctx->max_size <= 16 ? 1 : ctx->prm.precision == HERMITE_MIXED ? 4 : 2;
+    hermite::BatchShape sh{0, waves, 57};
     sh.workgroups = batch_resident(ctx, sh);
     return sh;
 }
