@@ -35,19 +35,24 @@ if ROOT not in sys.path:
 import hashlib
 
 FLOPS_PER_INTERACTION = {4: 60, 6: 97, 8: 144}
-# Sources that define the evaluation kernels; the measured HBM traffic below
-# is reported only while their hash and the launch shape (which fixes the
-# split workspace) match what was profiled.
-KERNEL_SOURCES = ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/sym_kernels.hip",
-                  "paper_2006_02501_amd/csrc/pair_chain.h", "paper_2006_02501_amd/csrc/force_launch.h",
-                  "paper_2006_02501_amd/csrc/lane_moves.h"]
+# Sources that define the evaluation kernels, per j-source of the launch
+# shape; the measured HBM traffic and counter figures below are reported only
+# while the hash of the launch's sources and the launch shape (which fixes
+# the workspace) match what was profiled.
+KERNEL_SOURCES = {
+    "pairs": ["paper_2006_02501_amd/csrc/sym_kernels.hip", "paper_2006_02501_amd/csrc/pair_chain.h",
+              "paper_2006_02501_amd/csrc/lane_moves.h", "paper_2006_02501_amd/csrc/force_launch.h"],
+    "lds": ["paper_2006_02501_amd/csrc/force_kernels.hip", "paper_2006_02501_amd/csrc/pair_chain.h",
+            "paper_2006_02501_amd/csrc/force_launch.h"],
+}
+KERNEL_SOURCES["scalar"] = KERNEL_SOURCES["lds"]
 # HBM bytes per evaluation (evaluation kernel and its reduction, plus the
 # j-record packing of the scalar source), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this benchmark,
 # each scaled by the counter's reading for a 256 MiB device copy.
 MEASURED_TRAFFIC = {
     "fp64": {
-        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+        "sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -58,7 +63,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 118403751
     },
     "mixed": {
-        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+        "sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -69,7 +74,7 @@ MEASURED_TRAFFIC = {
         "write_bytes": 103809024
     },
     "split": {
-        "sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+        "sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
         "launch": {
             "i_per_thread": 1,
             "j_split": 0,
@@ -87,13 +92,13 @@ MEASURED_TRAFFIC = {
 # times 64 lanes, over the N (N - 1) / 2 pairs of one 16k-disc evaluation);
 # reported only while the kernel sources and launch shape match.
 MEASURED_COUNTERS = {
-    "fp64": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+    "fp64": {"sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
              "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
              "valu_instr_per_pair": 126.6, "fp64_flops_per_pair": 158.2, "fp32_flops_per_pair": 0.0},
-    "mixed": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+    "mixed": {"sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
               "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
               "valu_instr_per_pair": 123.9, "fp64_flops_per_pair": 12.8, "fp32_flops_per_pair": 138.0},
-    "split": {"sources_sha256": "3ee786ed6b2a42b96aaa81721db1f584ee2277c7ca551f43ea2d07259ee9698c",
+    "split": {"sources_sha256": "fd13a82f38b7ede12389da71a2fb7d40533429021f6046729d16344d6647cf15",
               "launch": {"i_per_thread": 1, "j_split": 0, "j_source": "pairs", "wg_waves": 4},
               "valu_instr_per_pair": 141.7, "fp64_flops_per_pair": 68.5, "fp32_flops_per_pair": 91.0},
 }
@@ -118,9 +123,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sources_hash():
+def kernel_sources_hash(j_source="pairs"):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[j_source]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -128,7 +133,7 @@ def kernel_sources_hash():
 
 def _measured(table, precision, launch):
     t = (table or {}).get(precision)
-    if not t or t["sources_sha256"] != kernel_sources_hash() or t["launch"] != launch:
+    if not t or not launch or t["launch"] != launch or t["sources_sha256"] != kernel_sources_hash(launch["j_source"]):
         return None
     return t
 
@@ -693,6 +698,22 @@ def other_configs():
                 b.record()
             torch.cuda.synchronize()
             t_eval = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+            share = None
+            if name == "large_disc":
+                # one GPU's share of an 8-way division by i (hermite_force_derivs_range:
+                # N/8 i-particles against all N, the one-sided kernels)
+                ni = n // 8
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                h.force_derivs_range(st, 0, ni)
+                b.record()
+                torch.cuda.synchronize()
+                t_share = a.elapsed_time(b) / 1e3
+                tf = FLOPS_PER_INTERACTION[order] * ni * (n - 1) / t_share / 1e12
+                share = {"i_particles": ni, "j_particles": n, "eval_ms": t_share * 1e3,
+                         "interactions_per_s": ni * (n - 1) / t_share,
+                         "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                                      "frac": tf / PEAK_TFLOPS[prec]}}
             t0 = time.perf_counter()
             for _ in range(steps):
                 h.step(st, dt, n_iter)
@@ -709,6 +730,8 @@ def other_configs():
                          "ms_per_step": t_steps / steps * 1e3,
                          "step_interactions_per_s": steps * n_iter * inter / t_steps,
                          "energy_rel_change": (E1 - E0) / abs(E0)}
+            if share:
+                res[prec]["share_of_8_by_i"] = share
             log("    %s %s: eval %.2f ms (%.3e interactions/s, %.2f of peak), step %.2f ms"
                 % (name, prec, t_eval * 1e3, inter / t_eval, tflops / PEAK_TFLOPS[prec], t_steps / steps * 1e3))
         out[name] = res

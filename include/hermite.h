@@ -157,6 +157,16 @@ hermite_status hermite_predict(hermite_ctx *ctx, hermite_state *s, double dt);
  * Self terms are excluded by index.  Writes s->eval. */
 hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s);
 
+/* The same evaluation for the i-particles [i0, i0 + ni) only, each against
+ * every j != i: the share of one GPU when the particles are divided among
+ * GPUs by i (all the paths gathered on every GPU).  Writes s->eval at those
+ * positions ([p+1][3][n] layout) and leaves the others alone.  It takes the
+ * context's launch shape when that is one-sided (j_source 0 or 1); with
+ * j_source 2 (every pair once, which has no one-sided form) the LDS source
+ * with two i-particles per lane (FP64, split) or the scalar source with one
+ * (mixed).  E_ARG for a range outside [0, n). */
+hermite_status hermite_force_derivs_range(hermite_ctx *ctx, hermite_state *s, int64_t i0, int64_t ni);
+
 /* Modified corrector (Eq. 6-8; Eq. 22-24 for the default corrector) from
  * the start-of-step state (pos, vel, deriv[0..p]) and s->eval:
  *   v1 = v0 + sum_{k=0..p}   cv_k (a1^(k) +- a0^(k)) dt^(k+1)

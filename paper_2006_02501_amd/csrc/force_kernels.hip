@@ -222,7 +222,8 @@ __device__ __forceinline__ void reduce_waves(double *buf, int wave, int lane, do
 template <int K, Chain CH, int IPT, int W, bool SHARE, bool QM>
 __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const double *__restrict__ mass, Path<K> path,
                                                           double G, double eps2, int64_t j_chunk, int k_first,
-                                                          double *__restrict__ out, double *__restrict__ qpart)
+                                                          double *__restrict__ out, double *__restrict__ qpart,
+                                                          int64_t i_base, int64_t i_lo, int64_t i_end)
 {
     constexpr int RS = row_stride<K>();
     constexpr int UNR = 2;
@@ -236,7 +237,11 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
     const int wave = tid / kWave, lane = tid % kWave;
     constexpr int ISTRIDE = SHARE ? kWave : kWave * W;
     constexpr int IBLK = ISTRIDE * IPT;
-    const int64_t ib0 = (int64_t)blockIdx.x * IBLK;
+    // i-particles [i_lo, i_end) against every j.  The i-blocks stay on the
+    // grid of the whole evaluation (i_base is a multiple of IBLK), so every
+    // i takes exactly the operations it takes there; lanes outside the range
+    // compute nothing that is stored.
+    const int64_t ib0 = i_base + (int64_t)blockIdx.x * IBLK;
     const int64_t ib1 = min(n, ib0 + (int64_t)IBLK);
     const int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
     const int64_t jend = min(n, jbeg + j_chunk);
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
-        const bool ok = ii[q] < n;
+        const bool ok = ii[q] >= i_lo && ii[q] < i_end;
         if constexpr (QM) {
             rm.gm[q] = ok ? G * mass[ii[q]] : 0.0;
             rm.q[q] = 0.0;
@@ -308,7 +313,7 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
         }
     }
 
-    store_rate<QM, IPT, W>(rm, ii, n, qpart);
+    store_rate<QM, IPT, W>(rm, ii, i_end, qpart);
     if constexpr (SHARE) {
         reduce_waves<K, IPT, W>(smem, wave, lane, acc);
         if (wave != 0) return;
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(kWave * W) void force_kernel(int64_t n, const doubl
     double *o = out + (int64_t)blockIdx.y * nv * 3 * n;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        if (ii[q] >= n) continue;
+        if (ii[q] < i_lo || ii[q] >= i_end) continue;
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
             if (k < k_first) continue;
@@ -471,14 +476,19 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
                                                                  Path<K> path, double eps2, int64_t j_chunk,
                                                                  double *__restrict__ out,
                                                                  const double *__restrict__ mass, double G,
-                                                                 double *__restrict__ qpart)
+                                                                 double *__restrict__ qpart, int64_t i_base,
+                                                                 int64_t i_lo, int64_t i_end)
 {
     __shared__ double red[SHARE ? (W - 1) * IPT * (K + 1) * 3 * kWave : 1];
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
     constexpr int ISTRIDE = SHARE ? kWave : kWave * W;
     constexpr int IBLK = ISTRIDE * IPT;
-    const int64_t ib0 = (int64_t)blockIdx.x * IBLK;
+    // i-particles [i_lo, i_end) against every j.  The i-blocks stay on the
+    // grid of the whole evaluation (i_base is a multiple of IBLK), so every
+    // i takes exactly the operations it takes there; lanes outside the range
+    // compute nothing that is stored.
+    const int64_t ib0 = i_base + (int64_t)blockIdx.x * IBLK;
     const int64_t ib1 = min(n, ib0 + (int64_t)IBLK);
     int64_t jbeg = (int64_t)blockIdx.y * j_chunk;
     int64_t jend = min(n, jbeg + j_chunk);
@@ -498,7 +508,7 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         ii[q] = ib0 + q * ISTRIDE + (SHARE ? lane : tid);
-        const bool ok = ii[q] < n;
+        const bool ok = ii[q] >= i_lo && ii[q] < i_end;
         if constexpr (QM) {
             rm.gm[q] = ok ? G * mass[ii[q]] : 0.0;
             rm.q[q] = 0.0;
@@ -519,7 +529,7 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
     stream_folded<K, CH, IPT, true, QM>(jrec, d0, d1, ii, xi, eps2, acc, accf, rm);
     stream_folded<K, CH, IPT, false, QM>(jrec, d1, jend, ii, xi, eps2, acc, accf, rm);
 
-    store_rate<QM, IPT, W>(rm, ii, n, qpart);
+    store_rate<QM, IPT, W>(rm, ii, i_end, qpart);
     if constexpr (SHARE) {
         reduce_waves<K, IPT, W>(red, wave, lane, acc);
         if (wave != 0) return;
@@ -527,7 +537,7 @@ __global__ __launch_bounds__(kWave * W) void force_stream_kernel(int64_t n, cons
     double *o = out + (int64_t)blockIdx.y * (K + 1) * 3 * n;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        if (ii[q] >= n) continue;
+        if (ii[q] < i_lo || ii[q] >= i_end) continue;
 #pragma unroll
         for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -546,6 +556,22 @@ __global__ void reduce_splits_kernel(int64_t count, int nsplit, const double *__
     out[e] = s;
 }
 
+// The split partials of i-particles [i_off, i_off + ni) only (an evaluation of
+// an i-range): element e = comp * ni + (i - i_off), comp over nc components.
+__global__ void reduce_splits_range_kernel(int64_t n, int64_t i_off, int64_t ni, int nc, int nsplit,
+                                           const double *__restrict__ partial, double *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nc * ni) return;
+    const int64_t comp = e / ni;
+    const int64_t idx = comp * n + i_off + (e - comp * ni);
+    const int64_t count = (int64_t)nc * n;
+    double s = partial[idx];
+#pragma unroll 8
+    for (int sp = 1; sp < nsplit; ++sp) s += partial[(int64_t)sp * count + idx];
+    out[idx] = s;
+}
+
 // Workgroups of a launch (each writes one rate maximum when QM).
 template <int IPT, int W, bool SHARE>
 int64_t grid_blocks(int64_t n, int nsplit)
@@ -554,11 +580,14 @@ int64_t grid_blocks(int64_t n, int nsplit)
     return (n + ib - 1) / ib * nsplit;
 }
 
+// i-particles of a launch: [i_off, i_off + i_count()) (all n by default)
+int64_t i_count(const ForceArgs &a) { return a.i_cnt < 0 ? a.n : a.i_cnt; }
+
 template <int IPT, int W, bool SHARE, bool QM>
 bool rate_fits(const ForceArgs &a, int nsplit)
 {
     if constexpr (!QM) return true;
-    const int64_t nb = grid_blocks<IPT, W, SHARE>(a.n, nsplit);
+    const int64_t nb = grid_blocks<IPT, W, SHARE>(i_count(a), nsplit);
     if (nb > a.qpart_cap) return false;
     if (a.q_count) *a.q_count = (int)nb;
     return true;
@@ -571,9 +600,10 @@ hipError_t launch_lds(const ForceArgs &a, int nsplit, int64_t j_chunk, double *d
     Path<K> path;
     for (int k = 0; k <= K; ++k) path.p[k] = a.path[k];
     const int64_t ib = iblock_size(W, SHARE, IPT);
-    dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
+    const int64_t ni = i_count(a), base = a.i_off / ib * ib;
+    dim3 grid((unsigned)((a.i_off + ni - base + ib - 1) / ib), (unsigned)nsplit);
     hipLaunchKernelGGL((force_kernel<K, CH, IPT, W, SHARE, QM>), grid, dim3(kWave * W), 0, st, a.n, a.mass, path,
-                       a.G, a.eps2, j_chunk, a.k_first, dst, a.qpart);
+                       a.G, a.eps2, j_chunk, a.k_first, dst, a.qpart, base, a.i_off, a.i_off + ni);
     return hipGetLastError();
 }
 
@@ -588,9 +618,11 @@ hipError_t launch_stream(const ForceArgs &a, int nsplit, int64_t j_chunk, double
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t ib = iblock_size(W, SHARE, IPT);
-    dim3 grid((unsigned)((a.n + ib - 1) / ib), (unsigned)nsplit);
+    const int64_t ni = i_count(a), base = a.i_off / ib * ib;
+    dim3 grid((unsigned)((a.i_off + ni - base + ib - 1) / ib), (unsigned)nsplit);
     hipLaunchKernelGGL((force_stream_kernel<K, CH, IPT, W, SHARE, QM>), grid, dim3(kWave * W), 0, st, a.n,
-                       (const double *)a.jrec, path, a.eps2, j_chunk, dst, a.mass, a.G, a.qpart);
+                       (const double *)a.jrec, path, a.eps2, j_chunk, dst, a.mass, a.G, a.qpart, base, a.i_off,
+                       a.i_off + ni);
     return hipGetLastError();
 }
 
@@ -684,8 +716,12 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, 
     if (nv <= 0 || a.K >= kMaxPath) return hipErrorInvalidValue;
     const bool generic = chain == Chain::Generic;
     if (!generic && (a.k_first != 0 || a.K > 3)) return hipErrorInvalidValue;
+    const bool ranged = a.i_off != 0 || a.i_cnt >= 0;
+    if (ranged && (a.i_off < 0 || a.i_cnt < 0 || a.i_off + a.i_cnt > a.n || a.qpart)) return hipErrorInvalidValue;
+    if (ranged && a.i_cnt == 0) return hipSuccess;
     if (sh.jsource == JSource::Pairs) {
-        if (generic || sh.ipt != 1 || sh.waves != 4) return hipErrorInvalidValue;
+        // every pair once covers all bodies; an i-range takes the one-sided kernels
+        if (generic || sh.ipt != 1 || sh.waves != 4 || ranged) return hipErrorInvalidValue;
         return launch_force_pairs(a, chain, st);
     }
     if (!generic && sh.jsource == JSource::Scalar && !a.jrec) return hipErrorInvalidValue;
@@ -716,6 +752,12 @@ hipError_t launch_force(const ForceArgs &a, Chain chain, const LaunchShape &sh, 
         default: e = dispatch<Chain::Generic, false>(a, sh, nsplit, j_chunk, dst, st); break;
     }
     if (e != hipSuccess || nsplit == 1) return e;
+    if (ranged) {
+        const int64_t cnt = (int64_t)nv * 3 * a.i_cnt;
+        hipLaunchKernelGGL(reduce_splits_range_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a.n,
+                           a.i_off, a.i_cnt, nv * 3, nsplit, (const double *)a.partial, a.out);
+        return hipGetLastError();
+    }
     const int64_t blocks = (per_split + 255) / 256;
     hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)blocks), dim3(256), 0, st, per_split, nsplit,
                        (const double *)a.partial, a.out);

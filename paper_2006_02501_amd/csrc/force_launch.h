@@ -41,6 +41,11 @@ struct ForceArgs {
     // pairs of chunks sized to the workspace (as beyond kPairsMaxN) instead
     // of failing (no pair rate in that case).
     bool chunks_if_needed = false;
+    // Evaluation of the i-particles [i_off, i_off + i_cnt) only, against every
+    // j (one-sided kernels; i_cnt < 0: all n).  Outputs keep the [..][3][n]
+    // layout; the other positions are not written.
+    int64_t i_off = 0;
+    int64_t i_cnt = -1;
 };
 
 // Launch shape of the FP64 / mixed evaluation (the generic initialisation

@@ -196,10 +196,12 @@ bool pairs_rate(int64_t n) { return n <= hermite::kPairsMaxN; }
 
 hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, int K, int k_first,
                          const double *const *path, double *out, int ipt, int nsplit, int jsource, int waves,
-                         int *q_count = nullptr)
+                         int *q_count = nullptr, int64_t i0 = 0, int64_t ni = -1)
 {
     ForceArgs a{};
     a.n = s->n;
+    a.i_off = i0;
+    a.i_cnt = ni;
     a.mass = s->mass;
     for (int k = 0; k <= K; ++k) a.path[k] = path[k];
     a.K = K;
@@ -221,7 +223,7 @@ hermite_status run_force(hermite_ctx *ctx, const hermite_state *s, Chain chain, 
     hermite::LaunchShape sh{ipt, waves, src};
     if (src == hermite::JSource::Pairs && (chain == Chain::Generic || !pairs_fit(ctx, s->n)))
         return fail(ctx, HERMITE_E_ARG, "hermite: the every-pair-once evaluation does not fit this context's workspace");
-    if (nsplit <= 0) nsplit = hermite::auto_split(s->n, sh, chain == Chain::Generic);
+    if (nsplit <= 0) nsplit = hermite::auto_split(ni >= 0 ? ni : s->n, sh, chain == Chain::Generic);
     HIP_TRY(ctx, hermite::launch_force(a, chain, sh, nsplit, ctx->stream), "force kernel launch");
     return HERMITE_OK;
 }
@@ -551,6 +553,33 @@ hermite_status hermite_force_derivs(hermite_ctx *ctx, hermite_state *s)
     hermite_status st = check_state(ctx, s, false, true);
     if (st != HERMITE_OK) return st;
     return eval_path(ctx, s, nullptr);
+}
+
+hermite_status hermite_force_derivs_range(hermite_ctx *ctx, hermite_state *s, int64_t i0, int64_t ni)
+{
+    if (!ctx) return HERMITE_E_ARG;
+    if (ctx->batch || ctx->ensemble) return fail(ctx, HERMITE_E_ARG, "hermite: batched or ensemble context");
+    hermite_status st = check_state(ctx, s, false, true);
+    if (st != HERMITE_OK) return st;
+    if (i0 < 0 || ni < 0 || i0 > s->n || ni > s->n - i0)
+        return fail(ctx, HERMITE_E_ARG, "hermite: i-range outside [0, n)");
+    if (ni == 0) return HERMITE_OK;
+    // the context's one-sided launch shape; every pair once has no one-sided
+    // form, so that choice takes the LDS source with two i-particles per lane
+    // (FP64, split) or the scalar source with one (mixed)
+    int ipt = ctx->ipt, jsource = ctx->jsource, waves = ctx->waves, nsplit = ctx->nsplit;
+    if (jsource == 2) {
+        const bool mixed = ctx->prm.precision == HERMITE_MIXED;
+        ipt = mixed ? 1 : 2;
+        jsource = mixed ? 1 : 0;
+        waves = 4;
+        nsplit = 0;
+    }
+    const int p = ctx->p;
+    const int64_t n3 = 3 * s->n;
+    const double *path[hermite::kMaxPath] = {};
+    for (int k = 0; k <= p; ++k) path[k] = s->pred + k * n3;
+    return run_force(ctx, s, eval_chain(ctx), p, 0, path, s->eval, ipt, nsplit, jsource, waves, nullptr, i0, ni);
 }
 
 hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, int32_t last_iter)

@@ -61,6 +61,7 @@ _SIGS = {
     "hermite_init": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
     "hermite_predict": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double]),
     "hermite_force_derivs": (ctypes.c_int, [_P, ctypes.POINTER(StateC)]),
+    "hermite_force_derivs_range": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_int64, ctypes.c_int64]),
     "hermite_correct": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
     "hermite_step": (ctypes.c_int, [_P, ctypes.POINTER(StateC), ctypes.c_double, ctypes.c_int32]),
     "hermite_potential": (ctypes.c_int, [_P, ctypes.POINTER(StateC), _P]),
@@ -230,6 +231,11 @@ class Hermite:
 
     def force_derivs(self, st):
         _check(self.ctx, self.lib.hermite_force_derivs(self.ctx, ctypes.byref(st.c)))
+
+    def force_derivs_range(self, st, i0, ni):
+        """The evaluation for i-particles [i0, i0 + ni) against all j (one GPU's
+        share of an i-sharded evaluation); the rest of st.eval is left alone."""
+        _check(self.ctx, self.lib.hermite_force_derivs_range(self.ctx, ctypes.byref(st.c), int(i0), int(ni)))
 
     def correct(self, st, dt, last_iter):
         _check(self.ctx, self.lib.hermite_correct(self.ctx, ctypes.byref(st.c), float(dt), 1 if last_iter else 0))

@@ -69,6 +69,7 @@ def test_null_context_calls():
     assert lib.hermite_init(None, ctypes.byref(s)) == -1
     assert lib.hermite_predict(None, ctypes.byref(s), 0.1) == -1
     assert lib.hermite_force_derivs(None, ctypes.byref(s)) == -1
+    assert lib.hermite_force_derivs_range(None, ctypes.byref(s), 0, 1) == -1
     assert lib.hermite_correct(None, ctypes.byref(s), 0.1, 1) == -1
     assert lib.hermite_step(None, ctypes.byref(s), 0.1, 3) == -1
     assert lib.hermite_batch_run(None, ctypes.byref(s), None, 1, 1) == -1

@@ -26,9 +26,9 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_table_matches_sources_and_shapes():
     b = _bench_module()
-    h = b.kernel_sources_hash()
     for prec in ("fp64", "mixed", "split"):
         t = b.MEASURED_TRAFFIC[prec]
+        h = b.kernel_sources_hash(t["launch"]["j_source"])
         assert t["fetch_bytes"] > 0 and t["write_bytes"] > 0
         assert t["launch"]["j_source"] in b.JSOURCES
         # reported only for the profiled sources and shape
@@ -48,9 +48,9 @@ def test_peaks_and_flop_counts():
 
 def test_counter_table_matches_sources_and_shapes():
     b = _bench_module()
-    h = b.kernel_sources_hash()
     for prec in ("fp64", "mixed", "split"):
         t = b.MEASURED_COUNTERS[prec]
+        h = b.kernel_sources_hash(t["launch"]["j_source"])
         assert t["valu_instr_per_pair"] > 0 and t["fp64_flops_per_pair"] > 0
         ex = b.executed_work(prec, t["launch"], 16384, 5e-4, 3e13)
         if t["sources_sha256"] == h:
