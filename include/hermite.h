@@ -193,12 +193,17 @@ hermite_status hermite_step(hermite_ctx *ctx, hermite_state *s, double dt, int32
  * bodies without softening, non-finite positions).
  *
  * hermite_step_symmetric: one P(EC)^n step whose length is chosen implicitly
- * as the iteration proceeds: H_- = H(x0) at the start, the prediction with
- * dt = direction * H_-, and the correction of iteration k with
- *   dt_k = direction * (H_- + H_+,k) / 2,
- * H_+,k = H at iteration k's evaluation point (the predicted x, then the
- * previous iteration's corrected x), so that converged iterations give a step
- * that is the same taken forwards or backwards.  The step length stays on the
+ * as the iteration proceeds, dt = direction * (H_- + H_+) / 2 with H at the
+ * start and at the end of the step.  H_- = H(x0); the Taylor prediction for
+ * dt = direction * H_- gives a first end point, H_+ there gives dt_1, and the
+ * prediction is redone for dt_1.  Iteration k evaluates at its path, which
+ * lies at t0 + dt_k, and corrects with that same dt_k (the corrector's end
+ * values belong to the end of the step it makes, Eq. 4-8).  Before the next
+ * iteration, H_+ at this evaluation point gives dt_(k+1) and the iterate
+ * (x1, v1, a1^(0..p)) is moved to t0 + dt_(k+1) along its Taylor series to
+ * form the next path.  Converged iterations give a step that is the same
+ * taken forwards or backwards.  The step taken is the last correction's dt,
+ * which stays on the
  * device between launches; at the end it is copied back (synchronises),
  * added to s->t and stored in *dt_taken (host, may be NULL).
  * direction is +1 (forwards) or -1 (backwards).  E_ARG for n < 2, n_iter < 1,

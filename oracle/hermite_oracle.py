@@ -45,10 +45,13 @@ Readings where the paper is silent (frozen identically in the HIP path):
   R3  P(EC)^n iteration k >= 2 evaluates at the corrected (x1, v1) with the
       relative a, adot taken from iteration k-1's evaluation.
   R6  the self term is excluded by index, never by distance.
-  R21 variable step (Sec. 3.3): H_- at the start of the step, the prediction
-      with dt = H_-; iteration k corrects with dt = (H_- + H_+)/2, H_+ taken
-      at iteration k's evaluation point (the latest estimate of the end of
-      the step).  Converged iterations give the time-symmetric step.
+  R21 variable step (Sec. 3.3): H_- at the start of the step; a first
+      prediction with dt = H_- gives H_+ at its end point and dt_1 =
+      (H_- + H_+)/2, and the prediction is redone for dt_1.  Every iteration
+      corrects with the dt whose end point it evaluated (the corrector's end
+      values belong to t0 + dt, Eq. 4-8); H_+ at that evaluation point gives
+      the next dt, and the iterate is moved to the new end point along its own
+      Taylor series.  Converged iterations give the time-symmetric step.
   R22 compensated summation (Sec. 3.2, for the time integration): x, v and t
       each carry a Kahan compensation term; the corrector adds its increments
       dv, dx (and the step adds dt) through it.  Every iterate of a step uses
@@ -500,29 +503,48 @@ def _finish(st, p, dt, a0, a1, x1, v1, newcomp):
         st.t, st.tc = kahan_add(st.t, st.tc, dt)
 
 
+def shift_iterate(p, d, x1, v1, a1):
+    """The path x^(0..p) at t1 + d from the iterate at t1 (reading R21).
+
+    The iterate's own Taylor series about t1, with x^(0) = x1, x^(1) = v1 and
+    x^(k+2) = a1^(k) for k = 0..p:  path_f = sum_k x^(f+k) d^k / k!.  With
+    d = 0 it is (x1, v1, a1, adot1) as reading R3 takes it."""
+    xs = [x1, v1] + list(a1[: p + 1])
+    return [sum(xs[f + k] * (d ** k / factorial(k)) for k in range(len(xs) - f)) for f in range(p + 1)]
+
+
 def step_symmetric(st, eta, n_iter, corrector="modified", G=1.0, eps2=0.0, direction=1.0, compensated=False):
     """One P(EC)^n step with the implicit time-symmetric step of Sec. 3.3
-    (reading R21).  H_- = H(x0) at the start; the prediction uses dt = H_-;
-    every evaluation also gives H at its evaluation point (the current
-    estimate of the end of the step, H_+), and that iteration's correction uses
-    dt = (H_- + H_+)/2.  ``direction`` = -1 integrates backwards.
-    Returns the dt of the last correction (the step actually taken)."""
+    (reading R21): dt = (H_- + H_+)/2 with H (Eq. 25) at the start and at
+    the end of the step.
+
+    H_- = H(x0).  The Taylor prediction for dt = H_- gives a first end point
+    and H_+ there, hence dt_1 = (H_- + H_+)/2, and the prediction is redone
+    for dt_1.  Iteration k evaluates a1 at its path, which lies at t0 + dt_k,
+    and corrects with that same dt_k, so that every correction takes a1 at
+    the end of the step it makes (the end values of Eq. 4-8).  Before the
+    next iteration, H_+ at this evaluation point gives dt_(k+1), and the new
+    iterate is moved to t0 + dt_(k+1) along its own Taylor series.  The step
+    taken is the last correction's dt.  ``direction`` = -1 integrates
+    backwards.  Returns that dt."""
     if n_iter < 1:
         raise ValueError("n_iter must be >= 1")
     p = st.p
     a0 = st.derivs[: p + 1]
     Hm = step_criterion(st.mass, st.x, eta, G, eps2)
-    dt = direction * Hm
+    path = predict(p, direction * Hm, st.x, st.v, st.derivs)
+    dt = direction * 0.5 * (Hm + step_criterion(st.mass, path[0], eta, G, eps2))
     path = predict(p, dt, st.x, st.v, st.derivs)
     comp = (st.cx, st.cv) if compensated else None
-    for _ in range(n_iter):
+    for k in range(n_iter):
         out = pair_derivs(st.mass, path, K=p, G=G, eps2=eps2)
-        a1 = [out[k] for k in range(p + 1)]
-        Hp = step_criterion(st.mass, path[0], eta, G, eps2)
-        dt = direction * 0.5 * (Hm + Hp)
+        a1 = [out[j] for j in range(p + 1)]
         res = correct(p, dt, st.x, st.v, a0, a1, corrector, comp)
         x1, v1 = res[0], res[1]
-        path = [x1, v1] + a1[: p - 1]
+        if k + 1 < n_iter:
+            dt_next = direction * 0.5 * (Hm + step_criterion(st.mass, path[0], eta, G, eps2))
+            path = shift_iterate(p, dt_next - dt, x1, v1, a1)
+            dt = dt_next
     _finish(st, p, dt, a0, a1, x1, v1, res[2] if compensated else None)
     return dt
 

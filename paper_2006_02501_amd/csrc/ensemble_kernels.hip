@@ -15,10 +15,14 @@
 // added in a fixed order, so every thread forms the same a and the same
 // step, and the results do not depend on timing.
 //
-// Per step: prediction with dt = H_-, then n times (evaluation with the
-// pair rate fused in, H_+ = eta q^(-1/2) at the iterate, dt = (H_- + H_+)/2,
-// correction); the interpolated a^(p+1..2p-1); then one pass at the new x
-// for the next H_- and, once t is past the recording time, the energy.
+// Per step: prediction with dt = H_-, a pair-rate pass at the predicted
+// positions for H_+ there and the prediction redone for dt = (H_- + H_+)/2;
+// then n times (evaluation at t0 + dt with the pair rate fused in, correction
+// with that dt, and before the last iteration the next dt = (H_- + H_+)/2
+// from H_+ at this evaluation point, the iterate being moved to the new end
+// point along its Taylor series); the interpolated a^(p+1..2p-1); then one
+// pass at the new x for the next H_- and, once t is past the recording time,
+// the energy.
 #include "hermite_coeffs.h"
 #include "kernels.h"
 #include "pair_chain.h"
@@ -188,24 +192,25 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
     if (s.jp == 0) sm[s.islot] = gmi;
 
     // Barriers.  LDS is written in three places -- the iterate's path (sp),
-    // the j-part sums and wave maxima (red, rq), and the positions for the
+    // the j-part sums and wave maxima (red, rq), and the positions for a
     // criterion pass (sp[0]) -- each right after a barrier that every read of
     // the previous contents precedes, and read after the one barrier that
-    // follows the writes.  So an iteration takes two barriers and the
-    // end-of-step pass two.
+    // follows the writes.  So an iteration takes two barriers and each
+    // criterion pass (at the predicted end point, and at the new x after the
+    // step) two.
     //
-    // positions of the state into LDS, then the start-of-step criterion (and
-    // the energy, for E0 on a system's first call and for the records)
-    auto share_x = [&]() {
+    // positions into LDS, then a criterion pass at them (with the energy, for
+    // E0 on a system's first call and for the records)
+    auto share_pos = [&](const double (&xs)[3]) {
         if (s.jp == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sp[0][c][s.islot] = x[c];
+            for (int c = 0; c < 3; ++c) sp[0][c][s.islot] = xs[c];
         }
         __syncthreads();
     };
-    auto energy_and_rate = [&](bool want_pot, double &qmax, double &E) {
+    auto energy_and_rate = [&](const double (&xs)[3], bool want_pot, double &qmax, double &E) {
         double q, pot;
-        rate_pass(s, sp[0], sm, x, gmi, a.eps2, want_pot, q, pot);
+        rate_pass(s, sp[0], sm, xs, gmi, a.eps2, want_pot, q, pot);
         const double qw = wave_max(q);
         double ew = 0.0;
         if (want_pot) {
@@ -226,10 +231,10 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
         }
     };
 
-    share_x();   // (its barrier also publishes sm)
+    share_pos(x);   // (its barrier also publishes sm)
     double qm, E;
     const bool first = st.steps == 0;
-    energy_and_rate(first, qm, E);
+    energy_and_rate(x, first, qm, E);
     if (first) st.E0 = E;
     double Hm = cfg.eta / sqrt(qm);
     double t = st.t;
@@ -238,24 +243,41 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
 
     while (!failed && t < cfg.t_end && steps_here < a.max_steps) {
         double dt = Hm;
-        // predictor (Horner form, every stored derivative)
+        // predictor (Horner form, every stored derivative) for a step dt
         double path[K + 1][3];
+        auto predict_to = [&](double dt_p) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double xs[2 * P + 2];
-            xs[0] = x[c];
-            xs[1] = v[c];
+            for (int c = 0; c < 3; ++c) {
+                double xs[2 * P + 2];
+                xs[0] = x[c];
+                xs[1] = v[c];
 #pragma unroll
-            for (int k = 0; k < 2 * P; ++k) xs[k + 2] = d[k][c];
+                for (int k = 0; k < 2 * P; ++k) xs[k + 2] = d[k][c];
 #pragma unroll
-            for (int f = 0; f <= K; ++f) {
-                const int M = 2 * P + 1 - f;
-                double acc_ = xs[f + M];
+                for (int f = 0; f <= K; ++f) {
+                    const int M = 2 * P + 1 - f;
+                    double acc_ = xs[f + M];
 #pragma unroll
-                for (int k = M - 1; k >= 0; --k) acc_ = __builtin_fma(acc_, dt * kInvE[k + 1], xs[f + k]);
-                path[f][c] = acc_;
+                    for (int k = M - 1; k >= 0; --k) acc_ = __builtin_fma(acc_, dt_p * kInvE[k + 1], xs[f + k]);
+                    path[f][c] = acc_;
+                }
             }
+        };
+        // H_+ at the end point predicted for dt = H_-, then dt = (H_- + H_+)/2
+        predict_to(Hm);
+        {
+            double qp, unused;
+            const double xp[3] = {path[0][0], path[0][1], path[0][2]};
+            share_pos(xp);
+            energy_and_rate(xp, false, qp, unused);
+            const double Hp = cfg.eta / sqrt(qp);
+            if (!(Hp > 0.0) || !__builtin_isfinite(Hp)) {
+                failed = true;
+                break;
+            }
+            dt = 0.5 * (Hm + Hp);
         }
+        predict_to(dt);
         double a1[K + 1][3], x1[3], v1[3];
         for (int it = 0; it < cfg.n_iter; ++it) {
             if (s.jp == 0) {
@@ -310,16 +332,7 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
                     for (int p2 = 1; p2 < s.JP; ++p2) tsum += rr[p2 * s.NI];
                     a1[k][c] = tsum;
                 }
-            double qb = rq[0];
-#pragma unroll
-            for (int w = 1; w < kEnsWaves; ++w) qb = __builtin_fmax(qb, rq[w]);
-            const double Hp = cfg.eta / sqrt(qb);
-            if (!(Hp > 0.0) || !__builtin_isfinite(Hp)) {
-                failed = true;
-                break;
-            }
-            dt = 0.5 * (Hm + Hp);
-            // modified corrector: velocity first, then position
+            // modified corrector with this iteration's dt: velocity first, then position
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 double dv = 0.0;
@@ -339,13 +352,35 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
                 x1[c] = __builtin_fma(dx, dt, x[c]);
             }
             if (it + 1 < cfg.n_iter) {
+                // the next dt from H_+ at this evaluation point; the iterate,
+                // moved to t0 + next dt along its Taylor series
+                // (x1, v1, a1^(0..P)), is the next path
+                double qb = rq[0];
+#pragma unroll
+                for (int w = 1; w < kEnsWaves; ++w) qb = __builtin_fmax(qb, rq[w]);
+                const double Hp = cfg.eta / sqrt(qb);
+                if (!(Hp > 0.0) || !__builtin_isfinite(Hp)) {
+                    failed = true;
+                    break;
+                }
+                const double dtn = 0.5 * (Hm + Hp);
+                const double sh = dtn - dt;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    path[0][c] = x1[c];
-                    path[1][c] = v1[c];
+                    double xs[P + 3];
+                    xs[0] = x1[c];
+                    xs[1] = v1[c];
 #pragma unroll
-                    for (int m2 = 0; m2 <= K - 2; ++m2) path[2 + m2][c] = a1[m2][c];
+                    for (int k = 0; k <= P; ++k) xs[k + 2] = a1[k][c];
+#pragma unroll
+                    for (int f = 0; f <= K; ++f) {
+                        double acc_ = xs[P + 2];
+#pragma unroll
+                        for (int k = P + 1 - f; k >= 0; --k) acc_ = __builtin_fma(acc_, sh * kInvE[k + 1], xs[f + k]);
+                        path[f][c] = acc_;
+                    }
                 }
+                dt = dtn;
             }
         }
         if (failed) break;
@@ -378,8 +413,8 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
         ++steps_here;
         // next H_- at the new positions, with the energy once past rec_from
         const bool rec = t > cfg.rec_from;
-        share_x();
-        energy_and_rate(rec, qm, E);
+        share_pos(x);
+        energy_and_rate(x, rec, qm, E);
         Hm = cfg.eta / sqrt(qm);
         failed = !(Hm > 0.0) || !__builtin_isfinite(Hm);
         if (rec) {

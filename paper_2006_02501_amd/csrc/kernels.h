@@ -14,24 +14,31 @@ hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, con
                           const double *deriv, double *pred, hipStream_t st);
 
 // comp: [2][3][n] Kahan compensation of x and v, or null for plain addition.
-hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
-                          double *vel, double *deriv, const double *eval, double *pred, double *comp,
-                          hipStream_t st);
+// dtn_dev (variable step, not last): the next iteration's step length; the
+// next path is then the iterate moved from t0 + dt to t0 + dtn_dev[0] along
+// its Taylor series.  Null: the iterate itself is the next path.
+hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev,
+                          const double *dtn_dev, double *pos, double *vel, double *deriv, const double *eval,
+                          double *pred, double *comp, hipStream_t st);
 
 // Time-step criterion (Sec. 3.3): number of workgroup maxima the rate pass
 // writes for n particles (and its j-split).
 int qmax_partials(int64_t n, int *nsplit, int64_t *j_chunk);
 
-// H = eta q^(-1/2) at x ([3][n], n >= 2) into vs (device double[4]):
-// mode 0: vs[0] = H, vs[1] = dir H; mode 1: vs[2] = H, vs[1] = dir (vs[0] + H)/2;
-// vs[3] = 1 (and vs[1] = 0) once H is not finite and positive.
+// H = eta q^(-1/2) at x ([3][n], n >= 2) into vs (device double[kVsLen]):
+// mode 0: vs[0] = H, vs[slot] = dir H; mode 1: vs[2] = H,
+// vs[slot] = dir (vs[0] + H)/2; slot is 1 or 4 (the two step-length slots a
+// variable step alternates between); vs[3] = 1 (and vs[slot] = 0) once H is
+// not finite and positive.
+constexpr int kVsLen = 8;
 hipError_t launch_timestep(int64_t n, const double *mass, const double *x, double G, double eps2, double eta,
-                           double dir, int mode, double *qpart, int64_t qpart_cap, double *vs, hipStream_t st);
+                           double dir, int mode, int slot, double *qpart, int64_t qpart_cap, double *vs,
+                           hipStream_t st);
 
 // The same from count maxima already in qpart (an evaluation with the fused
 // pair rate wrote them).
-hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, double *vs,
-                                hipStream_t st);
+hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, int slot,
+                                double *vs, hipStream_t st);
 
 hipError_t launch_potential(int64_t n, const double *mass, const double *pos, double G, double eps2,
                             double *phi, hipStream_t st);

@@ -248,8 +248,8 @@ hermite_status alloc_timestep(hermite_ctx *ctx)
     // most (ceil(n/64)) * 64 splits
     ctx->qpart_cap = std::max<int64_t>((ctx->n_max + 255) / 256 + 4097, (ctx->n_max + 63) / 64 * 64);
     if (hipMalloc((void **)&ctx->qpart, ctx->qpart_cap * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
-    if (hipMalloc((void **)&ctx->vs, 4 * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
-    if (hipHostMalloc((void **)&ctx->host_vs, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if (hipMalloc((void **)&ctx->vs, hermite::kVsLen * sizeof(double)) != hipSuccess) return HERMITE_E_ALLOC;
+    if (hipHostMalloc((void **)&ctx->host_vs, hermite::kVsLen * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return HERMITE_E_ALLOC;
     return HERMITE_OK;
 }
@@ -589,8 +589,8 @@ hermite_status hermite_correct(hermite_ctx *ctx, hermite_state *s, double dt, in
     if (!good_dt(dt)) return fail(ctx, HERMITE_E_ARG, "hermite: dt must be finite and nonzero");
     hermite_status st = check_state(ctx, s, true, true);
     if (st != HERMITE_OK) return st;
-    HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, nullptr, s->pos, s->vel,
-                                         s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
+    HIP_TRY(ctx, hermite::launch_correct(ctx->p, ctx->prm.corrector, last_iter ? 1 : 0, s->n, dt, nullptr, nullptr,
+                                         s->pos, s->vel, s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
             "correct launch");
     if (last_iter) advance_time(ctx, s, dt);
     return HERMITE_OK;
@@ -625,10 +625,11 @@ hermite_status hermite_step_criterion(hermite_ctx *ctx, const hermite_state *s, 
     if (!h) return fail(ctx, HERMITE_E_ARG, "hermite: h is NULL");
     if (!std::isfinite(eta) || !(eta > 0.0)) return fail(ctx, HERMITE_E_ARG, "hermite: eta must be finite and > 0");
     if (s->n < 2) return fail(ctx, HERMITE_E_ARG, "hermite: the step criterion needs at least two particles");
-    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, 1.0, 0, ctx->qpart,
-                                          ctx->qpart_cap, ctx->vs, ctx->stream),
+    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, 1.0, 0, 1,
+                                          ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
             "step criterion launch");
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, hermite::kVsLen * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream),
             "step criterion copy");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "step criterion sync");
     *h = ctx->host_vs[0];
@@ -651,12 +652,21 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
     if (st != HERMITE_OK) return st;
     if (s->n < 2) return fail(ctx, HERMITE_E_ARG, "hermite: the step criterion needs at least two particles");
     const int p = ctx->p;
-    const double *dtp = ctx->vs + 1;
-    // H_- at the start, prediction with dt = s H_-
-    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, direction, 0,
-                                          ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
+    // The step length alternates between the device slots vs[1] and vs[4]:
+    // an iteration corrects with the one its path was formed for while the
+    // criterion at its evaluation point writes the next one into the other.
+    double *vs = ctx->vs;
+    // H_- at the start, a first prediction with dt = s H_-, H_+ at its end
+    // point, and the prediction for dt = s (H_- + H_+)/2
+    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pos, ctx->prm.G, ctx->prm.eps2, eta, direction, 0, 1,
+                                          ctx->qpart, ctx->qpart_cap, vs, ctx->stream),
             "step criterion launch");
-    HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, dtp, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
+    HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, vs + 1, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
+            "predict launch");
+    HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pred, ctx->prm.G, ctx->prm.eps2, eta, direction, 1, 4,
+                                          ctx->qpart, ctx->qpart_cap, vs, ctx->stream),
+            "step criterion launch");
+    HIP_TRY(ctx, hermite::launch_predict(p, s->n, 0.0, vs + 4, s->pos, s->vel, s->deriv, s->pred, ctx->stream),
             "predict launch");
     // FP64 and split evaluations take the pair rate along, and so does the
     // mixed every-pair-once evaluation (from its FP64 differences) while it is
@@ -665,33 +675,44 @@ hermite_status hermite_step_symmetric(hermite_ctx *ctx, hermite_state *s, double
     // separate FP64 pass
     const bool pairs = ctx->jsource == 2;
     const bool fused = pairs ? pairs_rate(s->n) : ctx->prm.precision != HERMITE_MIXED;
+    int cur = 4, nxt = 1;
     for (int it = 0; it < n_iter; ++it) {
-        // evaluation, H_+ at this iteration's evaluation point, dt = s (H_- + H_+)/2
-        if (fused) {
+        const bool last = it == n_iter - 1;
+        // evaluation at t0 + dt; before the last iteration also H_+ at this
+        // evaluation point, and from it the next dt = s (H_- + H_+)/2
+        if (last) {
+            st = eval_path(ctx, s, nullptr);
+            if (st != HERMITE_OK) return st;
+        } else if (fused) {
             int nq = 0;
             st = eval_path(ctx, s, &nq);
             if (st != HERMITE_OK) return st;
-            HIP_TRY(ctx, hermite::launch_timestep_fold(ctx->qpart, nq, eta, direction, 1, ctx->vs, ctx->stream),
+            HIP_TRY(ctx, hermite::launch_timestep_fold(ctx->qpart, nq, eta, direction, 1, nxt, vs, ctx->stream),
                     "step criterion launch");
         } else {
             st = eval_path(ctx, s, nullptr);
             if (st != HERMITE_OK) return st;
             HIP_TRY(ctx, hermite::launch_timestep(s->n, s->mass, s->pred, ctx->prm.G, ctx->prm.eps2, eta, direction,
-                                                  1, ctx->qpart, ctx->qpart_cap, ctx->vs, ctx->stream),
+                                                  1, nxt, ctx->qpart, ctx->qpart_cap, vs, ctx->stream),
                     "step criterion launch");
         }
-        HIP_TRY(ctx, hermite::launch_correct(p, ctx->prm.corrector, it == n_iter - 1 ? 1 : 0, s->n, 0.0, dtp, s->pos,
-                                             s->vel, s->deriv, s->eval, s->pred, comp_of(ctx, s), ctx->stream),
+        // correction with this iteration's dt; before the last iteration the
+        // iterate, moved to t0 + next dt, is the next path
+        HIP_TRY(ctx, hermite::launch_correct(p, ctx->prm.corrector, last ? 1 : 0, s->n, 0.0, vs + cur,
+                                             last ? nullptr : vs + nxt, s->pos, s->vel, s->deriv, s->eval, s->pred,
+                                             comp_of(ctx, s), ctx->stream),
                 "correct launch");
+        if (!last) std::swap(cur, nxt);
     }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, ctx->vs, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_vs, vs, hermite::kVsLen * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream),
             "step length copy");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "step length sync");
     if (ctx->host_vs[3] != 0.0)
         return fail(ctx, HERMITE_E_NONFINITE,
                     "hermite: step criterion not finite and positive (no pair with G (m_i + m_j) > 0, "
                     "coincident bodies without softening, or non-finite positions); state unchanged");
-    const double dt = ctx->host_vs[1];
+    const double dt = ctx->host_vs[cur];
     advance_time(ctx, s, dt);
     if (dt_taken) *dt_taken = dt;
     if (!ctx->prm.check_finite) return HERMITE_OK;

@@ -61,9 +61,16 @@ __global__ __launch_bounds__(kStepBlock) void predict_kernel(int64_t n3, double 
 // by Kahan's compensated summation (the option of Sec. 3.2): y = inc - c,
 // s' = s + y, c' = (s' - s) - y.  Every iterate uses the carried c; the last
 // iteration stores c'.
+// Before the last iteration the iterate becomes the next path: (x1, v1) and
+// the evaluated a, adot.  In a variable step (dtn_dev not null) the next
+// iteration's step length dtn differs from this one's, and the path is the
+// iterate moved to the new end point along its own Taylor series,
+// x^(f) + sum_k x^(f+k) d^k/k! with x^(0..P+2) = (x1, v1, a1^(0..P)) and
+// d = dtn - dt (Horner form, as the predictor).
 template <int P, int CORR>
 __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double dt_host,
-                                                             const double *__restrict__ dt_dev, int last,
+                                                             const double *__restrict__ dt_dev,
+                                                             const double *__restrict__ dtn_dev, int last,
                                                              double *__restrict__ pos,
                                                              double *__restrict__ vel, double *__restrict__ deriv,
                                                              const double *__restrict__ eval,
@@ -111,6 +118,22 @@ __global__ __launch_bounds__(kStepBlock) void correct_kernel(int64_t n3, double 
         x1 = __builtin_fma(dx, dt, x0);
     }
     if (!last) {
+        if (dtn_dev) {
+            const double d = dtn_dev[0] - dt;
+            double xs[P + 3];
+            xs[0] = x1;
+            xs[1] = v1;
+#pragma unroll
+            for (int k = 0; k <= P; ++k) xs[k + 2] = a1[k];
+#pragma unroll
+            for (int f = 0; f <= P; ++f) {
+                double t = xs[P + 2];
+#pragma unroll
+                for (int k = P + 1 - f; k >= 0; --k) t = __builtin_fma(t, d * kInv[k + 1], xs[f + k]);
+                pred[(int64_t)f * n3 + e] = t;
+            }
+            return;
+        }
         // next iterate: (x1, v1) and the evaluated a, adot as the relative path
         pred[e] = x1;
         pred[n3 + e] = v1;
@@ -192,14 +215,15 @@ __global__ __launch_bounds__(kStepBlock) void check_finite_kernel(const double *
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kStepBlock - 1) / kStepBlock); }
 
 template <int P>
-hipError_t correct_p(int corrector, int last, int64_t n3, double dt, const double *dt_dev, double *pos, double *vel,
-                     double *deriv, const double *eval, double *pred, double *comp, hipStream_t st)
+hipError_t correct_p(int corrector, int last, int64_t n3, double dt, const double *dt_dev, const double *dtn_dev,
+                     double *pos, double *vel, double *deriv, const double *eval, double *pred, double *comp,
+                     hipStream_t st)
 {
     const dim3 g(blocks_for(n3)), b(kStepBlock);
     switch (corrector) {
-        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
-        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
-        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, dt_dev, last, pos, vel, deriv, eval, pred, comp); break;
+        case 0: hipLaunchKernelGGL((correct_kernel<P, 0>), g, b, 0, st, n3, dt, dt_dev, dtn_dev, last, pos, vel, deriv, eval, pred, comp); break;
+        case 1: hipLaunchKernelGGL((correct_kernel<P, 1>), g, b, 0, st, n3, dt, dt_dev, dtn_dev, last, pos, vel, deriv, eval, pred, comp); break;
+        case 2: hipLaunchKernelGGL((correct_kernel<P, 2>), g, b, 0, st, n3, dt, dt_dev, dtn_dev, last, pos, vel, deriv, eval, pred, comp); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -222,16 +246,16 @@ hipError_t launch_predict(int p, int64_t n, double dt, const double *dt_dev, con
     return hipGetLastError();
 }
 
-hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev, double *pos,
-                          double *vel, double *deriv, const double *eval, double *pred, double *comp,
-                          hipStream_t st)
+hipError_t launch_correct(int p, int corrector, int last, int64_t n, double dt, const double *dt_dev,
+                          const double *dtn_dev, double *pos, double *vel, double *deriv, const double *eval,
+                          double *pred, double *comp, hipStream_t st)
 {
     const int64_t n3 = 3 * n;
     if (n3 <= 0) return hipSuccess;
     switch (p) {
-        case 1: return correct_p<1>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
-        case 2: return correct_p<2>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
-        case 3: return correct_p<3>(corrector, last, n3, dt, dt_dev, pos, vel, deriv, eval, pred, comp, st);
+        case 1: return correct_p<1>(corrector, last, n3, dt, dt_dev, dtn_dev, pos, vel, deriv, eval, pred, comp, st);
+        case 2: return correct_p<2>(corrector, last, n3, dt, dt_dev, dtn_dev, pos, vel, deriv, eval, pred, comp, st);
+        case 3: return correct_p<3>(corrector, last, n3, dt, dt_dev, dtn_dev, pos, vel, deriv, eval, pred, comp, st);
         default: return hipErrorInvalidValue;
     }
 }

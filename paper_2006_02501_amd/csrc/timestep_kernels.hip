@@ -84,14 +84,16 @@ __global__ __launch_bounds__(kQBlock) void qmax_kernel(int64_t n, const double *
     if (threadIdx.x == 0) qpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = best;
 }
 
-// vs[0] = H_- (start of step), vs[1] = dt, vs[2] = latest H_+, vs[3] = 1 once
-// the criterion is undefined (q not positive and finite: no massive pair,
-// coincident unsoftened bodies, or no finite position at all).  mode 0 starts a
-// step (H_- and dt = s H_-, clears vs[3]); mode 1 follows an evaluation
-// (H_+ and dt = s (H_- + H_+)/2).  Once vs[3] is set dt stays 0, which the
-// predictor and the corrector take as "leave the state as it is".
+// vs[0] = H_- (start of step), vs[2] = latest H_+, vs[3] = 1 once the
+// criterion is undefined (q not positive and finite: no massive pair,
+// coincident unsoftened bodies, or no finite position at all); vs[slot] (1 or
+// 4) receives a step length.  mode 0 starts a step (H_- and dt = s H_-,
+// clears vs[3]); mode 1 takes H_+ at an end point (dt = s (H_- + H_+)/2).
+// Once vs[3] is set the dt written is 0, which the predictor and the
+// corrector take as "leave the state as it is".
 __global__ __launch_bounds__(kQBlock) void timestep_kernel(const double *__restrict__ qpart, int count, double eta,
-                                                           double dir, int mode, double *__restrict__ vs)
+                                                           double dir, int mode, int slot,
+                                                           double *__restrict__ vs)
 {
     double q = 0.0;
     for (int k = threadIdx.x; k < count; k += kQBlock) q = qcombine(qpart[k], q);
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kQBlock) void timestep_kernel(const double *__restr
         vs[2] = H;
         dt = dir * (0.5 * (vs[0] + H));
     }
-    vs[1] = failed ? 0.0 : dt;
+    vs[slot] = failed ? 0.0 : dt;
     vs[3] = failed ? 1.0 : 0.0;
 }
 
@@ -131,9 +133,10 @@ int qmax_partials(int64_t n, int *nsplit_out, int64_t *j_chunk_out)
 }
 
 hipError_t launch_timestep(int64_t n, const double *mass, const double *x, double G, double eps2, double eta,
-                           double dir, int mode, double *qpart, int64_t qpart_cap, double *vs, hipStream_t st)
+                           double dir, int mode, int slot, double *qpart, int64_t qpart_cap, double *vs,
+                           hipStream_t st)
 {
-    if (n < 2) return hipErrorInvalidValue;
+    if (n < 2 || (slot != 1 && slot != 4)) return hipErrorInvalidValue;
     int ns = 1;
     int64_t chunk = n;
     const int count = qmax_partials(n, &ns, &chunk);
@@ -142,15 +145,15 @@ hipError_t launch_timestep(int64_t n, const double *mass, const double *x, doubl
     hipLaunchKernelGGL(qmax_kernel, dim3(nib, (unsigned)ns), dim3(kQBlock), 0, st, n, mass, x, G, eps2, chunk, qpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(timestep_kernel, dim3(1), dim3(kQBlock), 0, st, qpart, count, eta, dir, mode, vs);
+    hipLaunchKernelGGL(timestep_kernel, dim3(1), dim3(kQBlock), 0, st, qpart, count, eta, dir, mode, slot, vs);
     return hipGetLastError();
 }
 
-hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, double *vs,
-                                hipStream_t st)
+hipError_t launch_timestep_fold(const double *qpart, int count, double eta, double dir, int mode, int slot,
+                                double *vs, hipStream_t st)
 {
-    if (count < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(timestep_kernel, dim3(1), dim3(kQBlock), 0, st, qpart, count, eta, dir, mode, vs);
+    if (count < 1 || (slot != 1 && slot != 4)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(timestep_kernel, dim3(1), dim3(kQBlock), 0, st, qpart, count, eta, dir, mode, slot, vs);
     return hipGetLastError();
 }
 
