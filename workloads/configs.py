@@ -169,12 +169,14 @@ def large_disc(n=1048576):
                 steps=1, G=1.0, eps2=0.0)
 
 
-def disc100(n_bodies=100):
+def disc100(n_bodies=100, realization=0):
     """The paper's N-body test (Sec. 3.3, Table 1): 100 bodies of 1e-5 around a
     central mass 1, semi-major axes evenly log-spaced in [0.1, 10], e ~
     Rayleigh(0.06) and i ~ Rayleigh(0.12) (sigma_i = 2 sigma_e = 0.12), angles
-    uniform; eps = 1e-6, t_end = 100 pi.  Seeded: no seed is given."""
-    rng = _rng(5)
+    uniform; eps = 1e-6, t_end = 100 pi.  Seeded: no seed is given.
+    realization k > 0 draws the same recipe from another seed (the paper's
+    figures come from one unknown draw)."""
+    rng = _rng(5) if realization == 0 else _rng(100000 + int(realization))
     a = np.geomspace(0.1, 10.0, n_bodies)
     mass, x, v = _disc(rng, n_bodies + 1, 1.0, 1e-5, a, 0.06, 0.12)
     return dict(name="disc100", mass=mass, x=x, v=v, order=8, eps2=1e-12, t_end=100 * np.pi, G=1.0)
