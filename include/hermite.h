@@ -273,9 +273,8 @@ hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const
  * computed by one workgroup in a fixed order); waves and ring_min change the
  * order of the sums, hence the rounding.  E_ARG for values outside these
  * sets or a context that is not batched.  hermite_batch_get_launch reports
- * the shape in use (the creation default: 2 waves for HERMITE_FP64, 4 for
- * HERMITE_MIXED, 1 when no system has more than 16 bodies; ring_min 57;
- * every resident workgroup).
+ * the shape in use (the creation default: 2 waves, 1 when no system has
+ * more than 16 bodies; ring_min 57; every resident workgroup).
  *
  * hermite_batch_autotune times every supported shape (waves 1, 2, 4;
  * ring_min 57 or none; from half to all of the resident workgroups) for

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
     // a SIMD is latency-bound); the 8th-order FP64 kernel with compensation
     // would exceed 256 registers with them
     constexpr bool kTwo = W == 1 && !(P == 3 && !MIXED && COMP);
+    constexpr bool kEndInLoop = W >= 2;
     __shared__ double sp[NV][kLanes];      // path of the current iterate: [3 k + c][slot]
     __shared__ T sgm[kLanes];              // G m of every slot
     __shared__ double part[W][NV][kLanes]; // each wave's sums over its sweep steps
@@ -160,14 +161,14 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
         // the components this lane keeps: c = w + ci W, ci < NC, c < 3
         double x[NC], v[NC], d[2 * P][NC];
         // Kahan compensation of x and v (COMP, the option of Sec. 3.2): the
-        // carried terms, and the ones the latest correction produced
-        double cx[NC], cv[NC], ncx[NC], ncv[NC];
+        // carried terms
+        double cx[NC], cv[NC];
         double dt = 1.0;
         if (active) dt = dt_sys[li.sys];
 #pragma unroll
         for (int ci = 0; ci < NC; ++ci) {
             const int c = w + ci * W;
-            cx[ci] = cv[ci] = ncx[ci] = ncv[ci] = 0.0;
+            cx[ci] = cv[ci] = 0.0;
             if (c < 3 && active) {
                 x[ci] = pos[c * n + li.g];
                 v[ci] = vel[c * n + li.g];
@@ -219,7 +220,43 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                     sp[3 * f + c][l] = s;
                 }
             }
-            double a1[K + 1][NC], x1[NC], v1[NC];
+            // End of a system's step: interpolated higher derivatives
+            // (R2), then the new state.  With several waves per bin it runs
+            // inside the system's last iteration, so that nothing of the
+            // correction stays live through later sweeps (fewer registers);
+            // the lone-wave kernel, latency-bound on small systems, keeps the
+            // last correction and ends every lane's step once after the
+            // iterations (no divergent copies when systems of a bin take
+            // different iteration counts).
+            auto end_step = [&](int ci, const double (&a1)[K + 1], double x1, double v1, double ncx, double ncv) {
+                if constexpr (P == 2) {
+                    const double num = I6_A0[0] * d[0][ci] + I6_A1[0] * a1[0] +
+                                       (I6_A0[1] * d[1][ci] + I6_A1[1] * a1[1]) * dt +
+                                       (I6_A0[2] * d[2][ci] + I6_A1[2] * a1[2]) * (dt * dt);
+                    d[3][ci] = num / (dt * dt * dt);
+                }
+                if constexpr (P == 3) {
+                    const double tp[4] = {1.0, dt, dt * dt, dt * dt * dt};
+                    double n4 = 0.0, n5 = 0.0;
+#pragma unroll
+                    for (int m = 0; m <= 3; ++m) {
+                        n4 += (I8_4_A0[m] * d[m][ci] + I8_4_A1[m] * a1[m]) * tp[m];
+                        n5 += (I8_5_A0[m] * d[m][ci] + I8_5_A1[m] * a1[m]) * tp[m];
+                    }
+                    d[4][ci] = n4 / (tp[3] * dt);
+                    d[5][ci] = n5 / (tp[3] * tp[2]);
+                }
+#pragma unroll
+                for (int k = 0; k <= P; ++k) d[k][ci] = a1[k];
+                x[ci] = x1;
+                v[ci] = v1;
+                cx[ci] = ncx;
+                cv[ci] = ncv;
+            };
+            struct Last {
+                double a1[K + 1], x1, v1, ncx, ncv;
+            };
+            Last last[kEndInLoop ? 1 : NC];
             for (int it = 0; it < bin_iter; ++it) {
                 // the start-of-step state is redefined here for the compiler,
                 // so that no product of it is hoisted out of the iteration
@@ -344,80 +381,70 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 if (it >= my_iter) continue;
                 // Modified corrector for this lane's components: velocity
                 // first, then position; the sums of the waves added in order.
+                const bool fin = it + 1 == my_iter;
 #pragma unroll
                 for (int ci = 0; ci < NC; ++ci) {
                     const int c = w + ci * W;
                     if (c >= 3) break;
+                    double a1[K + 1];
 #pragma unroll
                     for (int k = 0; k <= K; ++k) {
                         double s = part[0][3 * k + c][l];
 #pragma unroll
                         for (int u = 1; u < W; ++u) s += part[u][3 * k + c][l];
-                        a1[k][ci] = s;
+                        a1[k] = s;
                     }
                     double dv = 0.0;
 #pragma unroll
                     for (int k = P; k >= 0; --k) {
-                        const double s = (k & 1) ? (a1[k][ci] - d[k][ci]) : (a1[k][ci] + d[k][ci]);
+                        const double s = (k & 1) ? (a1[k] - d[k][ci]) : (a1[k] + d[k][ci]);
                         dv = __builtin_fma(dv, dt, CV[P][k] * s);
                     }
+                    double x1, v1, ncx = 0.0, ncv = 0.0;
                     if constexpr (COMP) {
                         const double y = dv * dt - cv[ci];
-                        v1[ci] = v[ci] + y;
-                        ncv[ci] = (v1[ci] - v[ci]) - y;
+                        v1 = v[ci] + y;
+                        ncv = (v1 - v[ci]) - y;
                     } else {
-                        v1[ci] = __builtin_fma(dv, dt, v[ci]);
+                        v1 = __builtin_fma(dv, dt, v[ci]);
                     }
                     double dx = 0.0;
 #pragma unroll
                     for (int k = P + 1; k >= 1; --k) {
-                        const double s = (k & 1) ? (a1[k - 1][ci] - d[k - 1][ci]) : (a1[k - 1][ci] + d[k - 1][ci]);
+                        const double s = (k & 1) ? (a1[k - 1] - d[k - 1][ci]) : (a1[k - 1] + d[k - 1][ci]);
                         dx = __builtin_fma(dx, dt, cr.cx[k] * s);
                     }
-                    dx = __builtin_fma(dx, dt, cr.cx[0] * (v1[ci] + v[ci]));
+                    dx = __builtin_fma(dx, dt, cr.cx[0] * (v1 + v[ci]));
                     if constexpr (COMP) {
                         const double y = dx * dt - cx[ci];
-                        x1[ci] = x[ci] + y;
-                        ncx[ci] = (x1[ci] - x[ci]) - y;
+                        x1 = x[ci] + y;
+                        ncx = (x1 - x[ci]) - y;
                     } else {
-                        x1[ci] = __builtin_fma(dx, dt, x[ci]);
+                        x1 = __builtin_fma(dx, dt, x[ci]);
                     }
-                    if (it + 1 < my_iter) {
-                        sp[c][l] = x1[ci];
-                        sp[3 + c][l] = v1[ci];
+                    if (!fin) {
+                        sp[c][l] = x1;
+                        sp[3 + c][l] = v1;
 #pragma unroll
-                        for (int m = 0; m <= K - 2; ++m) sp[3 * (2 + m) + c][l] = a1[m][ci];
+                        for (int m = 0; m <= K - 2; ++m) sp[3 * (2 + m) + c][l] = a1[m];
+                    } else if constexpr (kEndInLoop) {
+                        end_step(ci, a1, x1, v1, ncx, ncv);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k <= K; ++k) last[ci].a1[k] = a1[k];
+                        last[ci].x1 = x1;
+                        last[ci].v1 = v1;
+                        last[ci].ncx = ncx;
+                        last[ci].ncv = ncv;
                     }
                 }
             }
-            // End of step: interpolated higher derivatives, then the new state.
+            if constexpr (!kEndInLoop) {
 #pragma unroll
-            for (int ci = 0; ci < NC; ++ci) {
-                const int c = w + ci * W;
-                if (c >= 3) break;
-                if constexpr (P == 2) {
-                    const double num = I6_A0[0] * d[0][ci] + I6_A1[0] * a1[0][ci] +
-                                       (I6_A0[1] * d[1][ci] + I6_A1[1] * a1[1][ci]) * dt +
-                                       (I6_A0[2] * d[2][ci] + I6_A1[2] * a1[2][ci]) * (dt * dt);
-                    d[3][ci] = num / (dt * dt * dt);
+                for (int ci = 0; ci < NC; ++ci) {
+                    if (w + ci * W >= 3) break;
+                    end_step(ci, last[ci].a1, last[ci].x1, last[ci].v1, last[ci].ncx, last[ci].ncv);
                 }
-                if constexpr (P == 3) {
-                    const double tp[4] = {1.0, dt, dt * dt, dt * dt * dt};
-                    double n4 = 0.0, n5 = 0.0;
-#pragma unroll
-                    for (int m = 0; m <= 3; ++m) {
-                        n4 += (I8_4_A0[m] * d[m][ci] + I8_4_A1[m] * a1[m][ci]) * tp[m];
-                        n5 += (I8_5_A0[m] * d[m][ci] + I8_5_A1[m] * a1[m][ci]) * tp[m];
-                    }
-                    d[4][ci] = n4 / (tp[3] * dt);
-                    d[5][ci] = n5 / (tp[3] * tp[2]);
-                }
-#pragma unroll
-                for (int k = 0; k <= P; ++k) d[k][ci] = a1[k][ci];
-                x[ci] = x1[ci];
-                v[ci] = v1[ci];
-                cx[ci] = ncx[ci];
-                cv[ci] = ncv[ci];
             }
         }
         if (active) {

@@ -410,7 +410,7 @@ int batch_resident(const hermite_ctx *ctx, const hermite::BatchShape &sh)
 // most 16 bodies take at most 8 sweep steps, too few to share: one wave.
 hermite::BatchShape default_batch_shape(const hermite_ctx *ctx)
 {
-    const int waves = ctx->max_size <= 16 ? 1 : ctx->prm.precision == HERMITE_MIXED ? 4 : 2;
+    const int waves = ctx->max_size <= 16 ? 1 : 2;
     hermite::BatchShape sh{0, waves, 57};
     sh.workgroups = batch_resident(ctx, sh);
     return sh;
