@@ -801,6 +801,8 @@ def main():
     ap.add_argument("--table1-iters", default="3,4", help="iteration counts of the 8th-order rows")
     ap.add_argument("--table1-realizations", type=int, default=1,
                     help="seeded draws of the disc per grid point, all in the same launch")
+    ap.add_argument("--table1-t-end", type=float, default=100 * np.pi,
+                    help="end time of the Table 1 runs (the paper's is 100 pi)")
     ap.add_argument("--eta", type=float, default=0.4,
                     help="variable-step accuracy parameter (0.4 gives dt near 2 pi / 2000 on this disc)")
     ap.add_argument("--no-per-system", action="store_true",
@@ -819,8 +821,8 @@ def main():
     if args.table1_only:
         etas = tuple(float(e) for e in args.table1_etas.split(","))
         iters = tuple(int(q) for q in args.table1_iters.split(","))
-        print(json.dumps({"table1": table1(etas=etas, iters=iters, realizations=args.table1_realizations)}),
-              flush=True)
+        print(json.dumps({"table1": table1(etas=etas, iters=iters, t_end=args.table1_t_end,
+                                           realizations=args.table1_realizations)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched": batched(args.batched_steps, per_system=not args.no_per_system,
@@ -921,7 +923,7 @@ def main():
         log("  table 1 ...")
         out["table1"] = table1(etas=tuple(float(e) for e in args.table1_etas.split(",")),
                                iters=tuple(int(q) for q in args.table1_iters.split(",")),
-                               realizations=args.table1_realizations)
+                               t_end=args.table1_t_end, realizations=args.table1_realizations)
     if not args.no_cpu_baseline:
         log("  cpu baseline (oracle) ...")
         base, acc, orb = cpu_baseline(w, lambda path: gpu_evaluations(w, path), fin)
