@@ -49,13 +49,14 @@ def _oracle_run(w, order, eta, n_iter, t_end, eps2, rec_from):
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_ensemble_matches_oracle(order):
     # one launch: a Kepler orbit (e = 0.7), the 100-body disc, a 7-body and a
-    # 128-body softened cluster, each with its own eta and n
+    # 128-body softened cluster, and a Kepler orbit (e = 0.3) with a single
+    # correction per step, each with its own eta and n
     _say("ensemble vs oracle order=%d" % order)
     kep = kepler_two_body(e=0.7, mean_anomaly=0.4)
-    systems = [kep, disc100(), _cluster(7, 1), _cluster(128, 2)]
-    etas = [0.05, 0.08, 0.1, 0.1]
-    iters = [4, 3, 2, 4]
-    t_ends = [0.3, 0.02, 0.5, 0.5]
+    systems = [kep, disc100(), _cluster(7, 1), _cluster(128, 2), kepler_two_body(e=0.3, mean_anomaly=1.1)]
+    etas = [0.05, 0.08, 0.1, 0.1, 0.05]
+    iters = [4, 3, 2, 4, 1]
+    t_ends = [0.3, 0.02, 0.5, 0.5, 0.3]
     eps2 = 1e-12
     mass, x, v, off = _concat(systems)
     eh = EnsembleHermite(order, off, eps2=eps2, device=DEV)
