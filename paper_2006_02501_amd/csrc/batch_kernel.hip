@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
     constexpr bool kEndInLoop = W >= 2;
     __shared__ double sp[NV][kLanes];      // path of the current iterate: [3 k + c][slot]
     __shared__ T sgm[kLanes];              // G m of every slot
-    __shared__ double part[W][NV][kLanes]; // each wave's sums over its sweep steps
+    // each wave's sums over its sweep steps (a lone wave keeps them in registers)
+    __shared__ double part[W == 1 ? 1 : W][W == 1 ? 1 : NV][W == 1 ? 1 : kLanes];
     __shared__ int next_bin;
     const int tid = threadIdx.x;
     // the wave index and every per-bin count below are the same in all lanes
@@ -364,18 +365,31 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 // lane l now holds the j-side sums of slot h: l + t1 (ring)
                 // or local body q + t1 (segments); a wave without steps
                 // holds zeros
-                const int h = ring ? ((l + t1) & (kLanes - 1)) : li.lo + (q + t1) % sz;
+                // A lone wave: each lane takes the j-side sums of its own slot
+                // from the lane holding them, l - t1 (ring) or local body
+                // q - t1 (segments), and adds them to its i-side sums (the
+                // same addition as through LDS below).
+                double own[W == 1 ? K + 1 : 1][3];
+                if constexpr (W == 1) {
+                    const int src = ring ? ((l - t1) & (kLanes - 1)) : li.lo + ((q - t1 % sz) % sz + sz) % sz;
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                    for (int k = 0; k <= K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) part[w][3 * k + c][l] = (double)acc[k][c];
-                // (the wave's LDS operations complete in order: the
-                // additions below see the writes above)
-                __builtin_amdgcn_wave_barrier();
+                        for (int c = 0; c < 3; ++c) own[k][c] = (double)acc[k][c] + (double)lane_from(4 * src, accj[k][c]);
+                } else {
+                    const int h = ring ? ((l + t1) & (kLanes - 1)) : li.lo + (q + t1) % sz;
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                    for (int k = 0; k <= K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) part[w][3 * k + c][h] += (double)accj[k][c];
+                        for (int c = 0; c < 3; ++c) part[w][3 * k + c][l] = (double)acc[k][c];
+                    // (the wave's LDS operations complete in order: the
+                    // additions below see the writes above)
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) part[w][3 * k + c][h] += (double)accj[k][c];
+                }
                 __syncthreads();   // every wave's sums are in part; sp may change
                 // a system past its own iteration count keeps its last iterate
                 if (it >= my_iter) continue;
@@ -389,10 +403,14 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                     double a1[K + 1];
 #pragma unroll
                     for (int k = 0; k <= K; ++k) {
-                        double s = part[0][3 * k + c][l];
+                        if constexpr (W == 1) {
+                            a1[k] = own[k][c];
+                        } else {
+                            double s = part[0][3 * k + c][l];
 #pragma unroll
-                        for (int u = 1; u < W; ++u) s += part[u][3 * k + c][l];
-                        a1[k] = s;
+                            for (int u = 1; u < W; ++u) s += part[u][3 * k + c][l];
+                            a1[k] = s;
+                        }
                     }
                     double dv = 0.0;
 #pragma unroll
