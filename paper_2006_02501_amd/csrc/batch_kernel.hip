@@ -365,31 +365,21 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 // lane l now holds the j-side sums of slot h: l + t1 (ring)
                 // or local body q + t1 (segments); a wave without steps
                 // holds zeros
-                // A lone wave: each lane takes the j-side sums of its own slot
-                // from the lane holding them, l - t1 (ring) or local body
-                // q - t1 (segments), and adds them to its i-side sums (the
-                // same addition as through LDS below).
+                // Each lane takes the j-side sums of its own slot from the
+                // lane holding them, l - t1 (ring) or local body q - t1
+                // (segments), and adds them to its i-side sums.  A lone wave
+                // keeps the result in registers; several waves put theirs in
+                // LDS for the component owners.
+                const int src = ring ? ((l - t1) & (kLanes - 1)) : li.lo + ((q - t1 % sz) % sz + sz) % sz;
                 double own[W == 1 ? K + 1 : 1][3];
-                if constexpr (W == 1) {
-                    const int src = ring ? ((l - t1) & (kLanes - 1)) : li.lo + ((q - t1 % sz) % sz + sz) % sz;
 #pragma unroll
-                    for (int k = 0; k <= K; ++k)
+                for (int k = 0; k <= K; ++k)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) own[k][c] = (double)acc[k][c] + (double)lane_from(4 * src, accj[k][c]);
-                } else {
-                    const int h = ring ? ((l + t1) & (kLanes - 1)) : li.lo + (q + t1) % sz;
-#pragma unroll
-                    for (int k = 0; k <= K; ++k)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) part[w][3 * k + c][l] = (double)acc[k][c];
-                    // (the wave's LDS operations complete in order: the
-                    // additions below see the writes above)
-                    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                    for (int k = 0; k <= K; ++k)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) part[w][3 * k + c][h] += (double)accj[k][c];
-                }
+                    for (int c = 0; c < 3; ++c) {
+                        const double s = (double)acc[k][c] + (double)lane_from(4 * src, accj[k][c]);
+                        if constexpr (W == 1) own[k][c] = s;
+                        else part[w][3 * k + c][l] = s;
+                    }
                 __syncthreads();   // every wave's sums are in part; sp may change
                 // a system past its own iteration count keeps its last iterate
                 if (it >= my_iter) continue;
