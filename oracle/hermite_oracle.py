@@ -33,7 +33,9 @@ What each function follows (section / equation of the paper):
 * ``step``                 Sec. 2 end / Sec. 3: P(EC)^n iteration.
 * ``kahan_add``            Sec. 3.2: compensated summation (reading R22).
 * ``step_criterion``,      Sec. 3.3, Eq. 25: the minimum two-body time scale
-  ``step_symmetric``       and the implicit time-symmetric step (reading R21).
+  ``step_symmetric``,      and the implicit time-symmetric step (reading R21),
+  ``shift_iterate``        whose iterates move to each new end point along their
+                           own Taylor series.
 * ``energy``, ``kepler_elements``  Sec. 3.1 diagnostics; eccentricity vector of
                            Appendix A (first equation).
 
