@@ -71,14 +71,15 @@ __global__ __launch_bounds__(kQBlock) void qmax_kernel(int64_t n, const double *
     double best = 0.0;
 #pragma unroll 4
     for (int64_t j = j0; j < j1; ++j) {
+        // every load of j is unconditional (a uniform scalar load); the pairs
+        // with j <= i (taken from their other end, or the self pair, whose
+        // rate may be inf or NaN without softening) are left out by a select
         const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
+        const double mj = mass[j];
         const double w = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         const double y = rsqrt64(w);
-        // j <= i (the pair is taken from its other end, or the self pair): a
-        // zero mass factor (0 or, unsoftened, 0 * inf = NaN; both leave the
-        // max as it is)
-        const double gm = (j <= i) ? 0.0 : G * (mass[j] + mi);
-        best = qcombine(gm * (y * y * y), best);
+        const double q = (G * (mj + mi)) * (y * y * y);
+        best = j > i ? qcombine(q, best) : best;
     }
     best = block_qmax(live ? best : 0.0);
     if (threadIdx.x == 0) qpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = best;
