@@ -30,7 +30,8 @@
 namespace hermite {
 namespace {
 
-constexpr int kEnsThreads = 512;
+constexpr int kEnsInitThreads = 512;    // the initialisation passes (once per run)
+constexpr int kEnsThreads = 1024;       // the run kernel: 16 wave64, four per SIMD
 constexpr int kEnsWaves = kEnsThreads / 64;
 constexpr int kEnsMaxN = 128;
 
@@ -46,16 +47,18 @@ struct Slots {
     int64_t g;   // global index of this thread's i-particle
 };
 
-__device__ __forceinline__ Slots slots_of(const int64_t *offsets, int sys, int tid)
+// exact: as many i-slots as bodies (threads beyond JP NI take no pairs);
+// else 64 or 128 slots, the system's size rounded up to whole waves.
+__device__ __forceinline__ Slots slots_of(const int64_t *offsets, int sys, int tid, int threads, bool exact)
 {
     Slots s;
     const int64_t off = offsets[sys];
     s.N = (int)(offsets[sys + 1] - off);
-    s.NI = s.N <= 64 ? 64 : 128;
-    s.JP = kEnsThreads / s.NI;
+    s.NI = exact ? s.N : s.N <= 64 ? 64 : 128;
+    s.JP = threads / s.NI;
     s.islot = tid % s.NI;
     s.jp = tid / s.NI;
-    s.live = s.islot < s.N;
+    s.live = s.islot < s.N && s.jp < s.JP;
     const int chunk = (s.N + s.JP - 1) / s.JP;
     s.jb = min(s.N, s.jp * chunk);
     s.je = min(s.N, s.jb + chunk);
@@ -82,7 +85,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // Generic-order initialisation pass K (1, 3, 5) for every system: outputs
 // k_first..K of the pair derivatives along path (x^(0..K) of all bodies).
 template <int K>
-__global__ __launch_bounds__(kEnsThreads) void ens_init_kernel(const int64_t *__restrict__ offsets, int64_t n,
+__global__ __launch_bounds__(kEnsInitThreads) void ens_init_kernel(const int64_t *__restrict__ offsets, int64_t n,
                                                                const double *__restrict__ mass, Path6Ptr path,
                                                                int k_first, double G, double eps2,
                                                                double *__restrict__ out)
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(kEnsThreads) void ens_init_kernel(const int64_t *__
     __shared__ double sm[kEnsMaxN];
     __shared__ double red[8][3][64];
     const int tid = threadIdx.x;
-    const Slots s = slots_of(offsets, blockIdx.x, tid);
+    const Slots s = slots_of(offsets, blockIdx.x, tid, kEnsInitThreads, false);
     if (s.jp == 0) {
         sm[s.islot] = s.live ? G * mass[s.g] : 0.0;
 #pragma unroll
@@ -141,17 +144,19 @@ __global__ __launch_bounds__(kEnsThreads) void ens_init_kernel(const int64_t *__
     }
 }
 
-// Pair pass at positions sp[0] (all bodies of the system in LDS): this
-// thread's maximum pair rate and, when want_pot, its part of sum_j G m_j / r.
-__device__ __forceinline__ void rate_pass(const Slots &s, const double (*sp0)[kEnsMaxN], const double *sm,
-                                          const double (&xi)[3], double gmi, double eps2, bool want_pot,
-                                          double &q, double &pot)
+// Pair pass at positions (X, Y, Z)[slot] (all bodies of the system in LDS):
+// this thread's maximum pair rate and, when want_pot, its part of
+// sum_j G m_j / r.
+__device__ __forceinline__ void rate_pass(const Slots &s, const double *X, const double *Y, const double *Z,
+                                          const double *sm, double gmi, double eps2, bool want_pot, double &q,
+                                          double &pot)
 {
+    const double xi0 = X[s.islot], xi1 = Y[s.islot], xi2 = Z[s.islot];
     q = 0.0;
     pot = 0.0;
 #pragma unroll 4
     for (int j = s.jb; j < s.je; ++j) {
-        const double dx = sp0[0][j] - xi[0], dy = sp0[1][j] - xi[1], dz = sp0[2][j] - xi[2];
+        const double dx = X[j] - xi0, dy = Y[j] - xi1, dz = Z[j] - xi2;
         const double w = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         const bool self = j == s.islot || !s.live;
         const double y = rsqrt64(self ? 1.0 : w);
@@ -161,60 +166,75 @@ __device__ __forceinline__ void rate_pass(const Slots &s, const double (*sp0)[kE
     }
 }
 
+// One system per workgroup of 1024 threads.  The per-body state x, v,
+// a^(0..2P-1) lives in LDS, and the per-body work (predictor, corrector,
+// shift of the iterate, interpolation) is done once per (body, component) by
+// the "owner" threads tid < 3 NI (slot tid % NI, component tid / NI).  The
+// evaluation is spread over all threads: thread t takes i-slot t % NI and the
+// j-part t / NI of the j-range (16 or 8 j-parts), with the i-path read from
+// LDS; its sums go to LDS and each owner adds the j-parts of its component in
+// j-part order.  Keeping the state out of the registers is what lets four
+// waves share a SIMD.
 template <int P, int CORR>
 __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
 {
     constexpr int K = P;
-    __shared__ double sp[K + 1][3][kEnsMaxN];
+    constexpr int NS = 2 + 2 * P;          // state per component: x, v, a^(0..2P-1)
+    __shared__ double sp[K + 1][3][kEnsMaxN];       // path of the current iterate
+    __shared__ double stl[3][NS][kEnsMaxN];          // state, [component][x, v, a^(k)][slot]
     __shared__ double sm[kEnsMaxN];
-    // j-part sums, [order*3 + component][j-part][i-slot]
-    __shared__ double red[(K + 1) * 3 * kEnsThreads];
+    // j-part sums, [order*3 + component][j-part * NI + i-slot]
+    __shared__ double red[(K + 1) * 3][kEnsThreads];
     __shared__ double rq[kEnsWaves], re[kEnsWaves];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int sys = blockIdx.x;
-    const Slots s = slots_of(a.offsets, sys, tid);
+    const Slots s = slots_of(a.offsets, sys, tid, kEnsThreads, true);
     const int64_t n = a.n, n3 = 3 * n;
+    const int64_t off = a.offsets[sys];
     const EnsembleCfg cfg = a.cfg[sys];
     EnsembleStatus st = a.status[sys];
     if (st.failed) return;
 
-    double x[3], v[3], d[2 * P][3];
+    // owner threads: (slot, component)
+    const bool owner = tid < 3 * s.NI;
+    const int oslot = tid % s.NI, oc = owner ? tid / s.NI : 0;
+    const bool olive = owner && oslot < s.N;
+    if (owner) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        x[c] = s.live ? a.pos[c * n + s.g] : 0.0;
-        v[c] = s.live ? a.vel[c * n + s.g] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 2 * P; ++k) d[k][c] = s.live ? a.deriv[k * n3 + c * n + s.g] : 0.0;
+        for (int f = 0; f < NS; ++f) {
+            double val = 0.0;
+            if (olive) {
+                const int64_t g = off + oslot;
+                val = f == 0 ? a.pos[oc * n + g] : f == 1 ? a.vel[oc * n + g] : a.deriv[(f - 2) * n3 + oc * n + g];
+            }
+            stl[oc][f][oslot] = val;
+        }
     }
     const double mi = s.live ? a.mass[s.g] : 0.0;
     const double gmi = a.G * mi;
     if (s.jp == 0) sm[s.islot] = gmi;
 
-    // Barriers.  LDS is written in three places -- the iterate's path (sp),
-    // the j-part sums and wave maxima (red, rq), and the positions for a
-    // criterion pass (sp[0]) -- each right after a barrier that every read of
-    // the previous contents precedes, and read after the one barrier that
-    // follows the writes.  So an iteration takes two barriers and each
-    // criterion pass (at the predicted end point, and at the new x after the
-    // step) two.
+    // Barriers.  LDS is written in four places -- the state (stl, by the
+    // owners at the end of a step), the path (sp), the j-part sums and wave
+    // maxima (red, rq, re) -- each right after a barrier that every read of
+    // the previous contents precedes, and read after the barrier that
+    // follows the writes.
     //
-    // positions into LDS, then a criterion pass at them (with the energy, for
-    // E0 on a system's first call and for the records)
-    auto share_pos = [&](const double (&xs)[3]) {
-        if (s.jp == 0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sp[0][c][s.islot] = xs[c];
-        }
-        __syncthreads();
-    };
-    auto energy_and_rate = [&](const double (&xs)[3], bool want_pot, double &qmax, double &E) {
+    // A criterion pass at the positions xs: the largest pair rate and, when
+    // want_pot, the energy (kinetic part from the state's v)
+    auto energy_and_rate = [&](const double *X, const double *Y, const double *Z, bool want_pot, double &qmax,
+                               double &E) {
         double q, pot;
-        rate_pass(s, sp[0], sm, xs, gmi, a.eps2, want_pot, q, pot);
+        rate_pass(s, X, Y, Z, sm, gmi, a.eps2, want_pot, q, pot);
         const double qw = wave_max(q);
         double ew = 0.0;
         if (want_pot) {
-            const double kin = (s.jp == 0 && s.live) ? 0.5 * mi * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) : 0.0;
+            double kin = 0.0;
+            if (s.jp == 0 && s.live) {
+                const double v0 = stl[0][1][s.islot], v1 = stl[1][1][s.islot], v2 = stl[2][1][s.islot];
+                kin = 0.5 * mi * (v0 * v0 + v1 * v1 + v2 * v2);
+            }
             ew = wave_sum(kin - 0.5 * mi * pot);
         }
         if (lane == 0) {
@@ -230,11 +250,19 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
             E += re[w];
         }
     };
+    // the owner's predictor: path f of component oc for a step dt_p
+    auto predict_f = [&](double dt_p, int f) {
+        const int M = 2 * P + 1 - f;
+        double acc_ = stl[oc][f + M][oslot];
+#pragma unroll
+        for (int k = M - 1; k >= 0; --k) acc_ = __builtin_fma(acc_, dt_p * kInvE[k + 1], stl[oc][f + k][oslot]);
+        return acc_;
+    };
 
-    share_pos(x);   // (its barrier also publishes sm)
+    __syncthreads();   // the state and sm are in LDS
     double qm, E;
     const bool first = st.steps == 0;
-    energy_and_rate(x, first, qm, E);
+    energy_and_rate(stl[0][0], stl[1][0], stl[2][0], first, qm, E);
     if (first) st.E0 = E;
     double Hm = cfg.eta / sqrt(qm);
     double t = st.t;
@@ -242,34 +270,13 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
     bool failed = !(Hm > 0.0) || !__builtin_isfinite(Hm);
 
     while (!failed && t < cfg.t_end && steps_here < a.max_steps) {
-        double dt = Hm;
-        // predictor (Horner form, every stored derivative) for a step dt
-        double path[K + 1][3];
-        auto predict_to = [&](double dt_p) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double xs[2 * P + 2];
-                xs[0] = x[c];
-                xs[1] = v[c];
-#pragma unroll
-                for (int k = 0; k < 2 * P; ++k) xs[k + 2] = d[k][c];
-#pragma unroll
-                for (int f = 0; f <= K; ++f) {
-                    const int M = 2 * P + 1 - f;
-                    double acc_ = xs[f + M];
-#pragma unroll
-                    for (int k = M - 1; k >= 0; --k) acc_ = __builtin_fma(acc_, dt_p * kInvE[k + 1], xs[f + k]);
-                    path[f][c] = acc_;
-                }
-            }
-        };
         // H_+ at the end point predicted for dt = H_-, then dt = (H_- + H_+)/2
-        predict_to(Hm);
+        if (owner) sp[0][oc][oslot] = predict_f(Hm, 0);
+        __syncthreads();
+        double dt;
         {
             double qp, unused;
-            const double xp[3] = {path[0][0], path[0][1], path[0][2]};
-            share_pos(xp);
-            energy_and_rate(xp, false, qp, unused);
+            energy_and_rate(sp[0][0], sp[0][1], sp[0][2], false, qp, unused);
             const double Hp = cfg.eta / sqrt(qp);
             if (!(Hp > 0.0) || !__builtin_isfinite(Hp)) {
                 failed = true;
@@ -277,84 +284,56 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
             }
             dt = 0.5 * (Hm + Hp);
         }
-        predict_to(dt);
-        double a1[K + 1][3], x1[3], v1[3];
+        if (owner) {
+#pragma unroll
+            for (int f = 0; f <= K; ++f) sp[f][oc][oslot] = predict_f(dt, f);
+        }
         for (int it = 0; it < cfg.n_iter; ++it) {
-            if (s.jp == 0) {
-#pragma unroll
-                for (int k = 0; k <= K; ++k)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) sp[k][c][s.islot] = path[k][c];
-            }
-            __syncthreads();
+            __syncthreads();   // the path is in sp; red and rq are free
             double acc[K + 1][3];
 #pragma unroll
             for (int k = 0; k <= K; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
             double q = 0.0;
-            // two pairs in flight where the registers allow it (not at 8th order)
-            constexpr int kUnr = K >= 3 ? 1 : 2;
-#pragma unroll kUnr
-            for (int j = s.jb; j < s.je; ++j) {
-                double r[3], vv[3], aa[3], jj[3];
+            {
+                double pi[K + 1][3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    r[c] = sp[0][c][j] - path[0][c];
-                    vv[c] = sp[1][c][j] - path[1][c];
-                    aa[c] = K >= 2 ? sp[K >= 2 ? 2 : 0][c][j] - path[K >= 2 ? 2 : 0][c] : 0.0;
-                    jj[c] = K >= 3 ? sp[K >= 3 ? 3 : 0][c][j] - path[K >= 3 ? 3 : 0][c] : 0.0;
+                for (int k = 0; k <= K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pi[k][c] = sp[k][c][s.islot];
+                for (int j = s.jb; j < s.je; ++j) {
+                    double r[3], vv[3], aa[3], jj[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = sp[0][c][j] - pi[0][c];
+                        vv[c] = sp[1][c][j] - pi[1][c];
+                        aa[c] = K >= 2 ? sp[K >= 2 ? 2 : 0][c][j] - pi[K >= 2 ? 2 : 0][c] : 0.0;
+                        jj[c] = K >= 3 ? sp[K >= 3 ? 3 : 0][c][j] - pi[K >= 3 ? 3 : 0][c] : 0.0;
+                    }
+                    const bool self = j == s.islot || !s.live;
+                    double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], a.eps2)));
+                    w = self ? 1.0 : w;
+                    const double m = self ? 0.0 : sm[j];
+                    const double rinv = rsqrt64(w);
+                    const double rinv2 = rinv * rinv;
+                    const double r3 = self ? 0.0 : rinv * rinv2;
+                    chain_accumulate<K, double>(r, vv, aa, jj, m * r3, rinv2, acc);
+                    q = __builtin_fmax(q, (gmi + m) * r3);
                 }
-                const bool self = j == s.islot || !s.live;
-                double w = __builtin_fma(r[0], r[0], __builtin_fma(r[1], r[1], __builtin_fma(r[2], r[2], a.eps2)));
-                w = self ? 1.0 : w;
-                const double m = self ? 0.0 : sm[j];
-                const double rinv = rsqrt64(w);
-                const double rinv2 = rinv * rinv;
-                const double r3 = self ? 0.0 : rinv * rinv2;
-                chain_accumulate<K, double>(r, vv, aa, jj, m * r3, rinv2, acc);
-                q = __builtin_fmax(q, (gmi + m) * r3);
             }
-            // j-part sums added in j-part order; the block's largest pair rate
 #pragma unroll
             for (int k = 0; k <= K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) red[((k * 3 + c) * s.JP + s.jp) * s.NI + s.islot] = acc[k][c];
+                for (int c = 0; c < 3; ++c) red[k * 3 + c][s.jp * s.NI + s.islot] = acc[k][c];
             const double qw = wave_max(q);
             if (lane == 0) rq[wave] = qw;
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k <= K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double *rr = red + (k * 3 + c) * s.JP * s.NI + s.islot;
-                    double tsum = rr[0];
-                    for (int p2 = 1; p2 < s.JP; ++p2) tsum += rr[p2 * s.NI];
-                    a1[k][c] = tsum;
-                }
-            // modified corrector with this iteration's dt: velocity first, then position
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double dv = 0.0;
-#pragma unroll
-                for (int k = P; k >= 0; --k) {
-                    const double sg = (k & 1) ? (a1[k][c] - d[k][c]) : (a1[k][c] + d[k][c]);
-                    dv = __builtin_fma(dv, dt, CV[P][k] * sg);
-                }
-                v1[c] = __builtin_fma(dv, dt, v[c]);
-                double dx = 0.0;
-#pragma unroll
-                for (int k = P + 1; k >= 1; --k) {
-                    const double sg = (k & 1) ? (a1[k - 1][c] - d[k - 1][c]) : (a1[k - 1][c] + d[k - 1][c]);
-                    dx = __builtin_fma(dx, dt, CX[CORR][P][k] * sg);
-                }
-                dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1[c] + v[c]));
-                x1[c] = __builtin_fma(dx, dt, x[c]);
-            }
-            if (it + 1 < cfg.n_iter) {
-                // the next dt from H_+ at this evaluation point; the iterate,
-                // moved to t0 + next dt along its Taylor series
-                // (x1, v1, a1^(0..P)), is the next path
+            __syncthreads();   // the sums and maxima are in LDS; sp may change
+            const bool last = it + 1 == cfg.n_iter;
+            double dtn = dt;
+            if (!last) {
+                // the next dt from H_+ at this evaluation point (every thread
+                // forms it from the same maxima)
                 double qb = rq[0];
 #pragma unroll
                 for (int w = 1; w < kEnsWaves; ++w) qb = __builtin_fmax(qb, rq[w]);
@@ -363,58 +342,87 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
                     failed = true;
                     break;
                 }
-                const double dtn = 0.5 * (Hm + Hp);
-                const double sh = dtn - dt;
+                dtn = 0.5 * (Hm + Hp);
+            }
+            if (owner) {
+                // a1 of this component, the j-parts added in order
+                double a1[K + 1];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int k = 0; k <= K; ++k) {
+                    const double *rr = &red[k * 3 + oc][oslot];
+                    double tsum = rr[0];
+                    for (int p2 = 1; p2 < s.JP; ++p2) tsum += rr[p2 * s.NI];
+                    a1[k] = tsum;
+                }
+                // modified corrector with this iteration's dt: velocity first, then position
+                const double x0 = stl[oc][0][oslot], v0 = stl[oc][1][oslot];
+                double d0[K + 1];
+#pragma unroll
+                for (int k = 0; k <= K; ++k) d0[k] = stl[oc][2 + k][oslot];
+                double dv = 0.0;
+#pragma unroll
+                for (int k = P; k >= 0; --k) {
+                    const double sg = (k & 1) ? (a1[k] - d0[k]) : (a1[k] + d0[k]);
+                    dv = __builtin_fma(dv, dt, CV[P][k] * sg);
+                }
+                const double v1 = __builtin_fma(dv, dt, v0);
+                double dx = 0.0;
+#pragma unroll
+                for (int k = P + 1; k >= 1; --k) {
+                    const double sg = (k & 1) ? (a1[k - 1] - d0[k - 1]) : (a1[k - 1] + d0[k - 1]);
+                    dx = __builtin_fma(dx, dt, CX[CORR][P][k] * sg);
+                }
+                dx = __builtin_fma(dx, dt, CX[CORR][P][0] * (v1 + v0));
+                const double x1 = __builtin_fma(dx, dt, x0);
+                if (!last) {
+                    // the iterate, moved to t0 + dtn along its Taylor series
+                    // (x1, v1, a1^(0..P)), is the next path
+                    const double sh = dtn - dt;
                     double xs[P + 3];
-                    xs[0] = x1[c];
-                    xs[1] = v1[c];
+                    xs[0] = x1;
+                    xs[1] = v1;
 #pragma unroll
-                    for (int k = 0; k <= P; ++k) xs[k + 2] = a1[k][c];
+                    for (int k = 0; k <= P; ++k) xs[k + 2] = a1[k];
 #pragma unroll
                     for (int f = 0; f <= K; ++f) {
                         double acc_ = xs[P + 2];
 #pragma unroll
                         for (int k = P + 1 - f; k >= 0; --k) acc_ = __builtin_fma(acc_, sh * kInvE[k + 1], xs[f + k]);
-                        path[f][c] = acc_;
+                        sp[f][oc][oslot] = acc_;
                     }
+                } else {
+                    // end of step: interpolated higher derivatives, the new state
+                    if constexpr (P == 2) {
+                        const double num = I6_A0[0] * d0[0] + I6_A1[0] * a1[0] + (I6_A0[1] * d0[1] + I6_A1[1] * a1[1]) * dt +
+                                           (I6_A0[2] * d0[2] + I6_A1[2] * a1[2]) * (dt * dt);
+                        stl[oc][2 + 3][oslot] = num / (dt * dt * dt);
+                    }
+                    if constexpr (P == 3) {
+                        const double tp[4] = {1.0, dt, dt * dt, dt * dt * dt};
+                        double n4 = 0.0, n5 = 0.0;
+#pragma unroll
+                        for (int m2 = 0; m2 <= 3; ++m2) {
+                            n4 += (I8_4_A0[m2] * d0[m2] + I8_4_A1[m2] * a1[m2]) * tp[m2];
+                            n5 += (I8_5_A0[m2] * d0[m2] + I8_5_A1[m2] * a1[m2]) * tp[m2];
+                        }
+                        stl[oc][2 + 4][oslot] = n4 / (tp[3] * dt);
+                        stl[oc][2 + 5][oslot] = n5 / (tp[3] * tp[2]);
+                    }
+#pragma unroll
+                    for (int k = 0; k <= P; ++k) stl[oc][2 + k][oslot] = a1[k];
+                    stl[oc][0][oslot] = x1;
+                    stl[oc][1][oslot] = v1;
                 }
-                dt = dtn;
             }
+            dt = dtn;
         }
         if (failed) break;
-        // end of step: interpolated higher derivatives, the new state
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if constexpr (P == 2) {
-                const double num = I6_A0[0] * d[0][c] + I6_A1[0] * a1[0][c] +
-                                   (I6_A0[1] * d[1][c] + I6_A1[1] * a1[1][c]) * dt +
-                                   (I6_A0[2] * d[2][c] + I6_A1[2] * a1[2][c]) * (dt * dt);
-                d[3][c] = num / (dt * dt * dt);
-            }
-            if constexpr (P == 3) {
-                const double tp[4] = {1.0, dt, dt * dt, dt * dt * dt};
-                double n4 = 0.0, n5 = 0.0;
-#pragma unroll
-                for (int m2 = 0; m2 <= 3; ++m2) {
-                    n4 += (I8_4_A0[m2] * d[m2][c] + I8_4_A1[m2] * a1[m2][c]) * tp[m2];
-                    n5 += (I8_5_A0[m2] * d[m2][c] + I8_5_A1[m2] * a1[m2][c]) * tp[m2];
-                }
-                d[4][c] = n4 / (tp[3] * dt);
-                d[5][c] = n5 / (tp[3] * tp[2]);
-            }
-#pragma unroll
-            for (int k = 0; k <= P; ++k) d[k][c] = a1[k][c];
-            x[c] = x1[c];
-            v[c] = v1[c];
-        }
         t += dt;
         ++steps_here;
         // next H_- at the new positions, with the energy once past rec_from
         const bool rec = t > cfg.rec_from;
-        share_pos(x);
-        energy_and_rate(x, rec, qm, E);
+        __syncthreads();   // the new state is in LDS
+        energy_and_rate(stl[0][0], stl[1][0], stl[2][0], rec, qm, E);
         Hm = cfg.eta / sqrt(qm);
         failed = !(Hm > 0.0) || !__builtin_isfinite(Hm);
         if (rec) {
@@ -427,14 +435,12 @@ __global__ __launch_bounds__(kEnsThreads) void ens_run_kernel(EnsembleArgs a)
             else st.rec_overflow = 1;
         }
     }
-    if (s.live && s.jp == 0) {
+    if (olive) {
+        const int64_t g = off + oslot;
+        a.pos[oc * n + g] = stl[oc][0][oslot];
+        a.vel[oc * n + g] = stl[oc][1][oslot];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            a.pos[c * n + s.g] = x[c];
-            a.vel[c * n + s.g] = v[c];
-#pragma unroll
-            for (int k = 0; k < 2 * P; ++k) a.deriv[k * n3 + c * n + s.g] = d[k][c];
-        }
+        for (int k = 0; k < 2 * P; ++k) a.deriv[k * n3 + oc * n + g] = stl[oc][2 + k][oslot];
     }
     if (tid == 0) {
         st.t = t;
@@ -456,15 +462,15 @@ hipError_t launch_ensemble_init(const int64_t *offsets, int32_t n_sys, int p, in
     path.p[0] = pos;
     path.p[1] = vel;
     for (int k = 0; k < 4; ++k) path.p[2 + k] = deriv + k * n3;
-    hipLaunchKernelGGL(ens_init_kernel<1>, dim3(n_sys), dim3(kEnsThreads), 0, st, offsets, n, mass, path, 0, G,
+    hipLaunchKernelGGL(ens_init_kernel<1>, dim3(n_sys), dim3(kEnsInitThreads), 0, st, offsets, n, mass, path, 0, G,
                        eps2, deriv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p < 2) return e;
-    hipLaunchKernelGGL(ens_init_kernel<3>, dim3(n_sys), dim3(kEnsThreads), 0, st, offsets, n, mass, path, 2, G,
+    hipLaunchKernelGGL(ens_init_kernel<3>, dim3(n_sys), dim3(kEnsInitThreads), 0, st, offsets, n, mass, path, 2, G,
                        eps2, deriv + 2 * n3);
     e = hipGetLastError();
     if (e != hipSuccess || p < 3) return e;
-    hipLaunchKernelGGL(ens_init_kernel<5>, dim3(n_sys), dim3(kEnsThreads), 0, st, offsets, n, mass, path, 4, G,
+    hipLaunchKernelGGL(ens_init_kernel<5>, dim3(n_sys), dim3(kEnsInitThreads), 0, st, offsets, n, mass, path, 4, G,
                        eps2, deriv + 4 * n3);
     return hipGetLastError();
 }
