@@ -5,15 +5,15 @@
 // 10^6 such steps; one launch carries a whole grid of them, one system per
 // CU).
 //
-// A workgroup is 512 threads (8 wave64).  Thread t takes the i-slot
-// t % NI and the j-part t / NI, NI = 64 or 128 (the system's size rounded up
-// to whole waves), so 8 or 4 threads share an i-particle and split its
-// j-range.  Every thread of an i-slot keeps the same copy of that particle's
-// state (x, v, a^(0..2p-1)) in VGPRs and runs the per-particle predictor and
-// corrector itself (O(N) work, repeated, so no broadcast is needed); the
-// evaluation's j-part sums and the pair-rate maxima meet in LDS and are
-// added in a fixed order, so every thread forms the same a and the same
-// step, and the results do not depend on timing.
+// A workgroup is 1024 threads (16 wave64, four per SIMD).  The state of the
+// system (x, v, a^(0..2p-1) of every body) lives in LDS; the per-body work
+// (predictor, corrector, the shift of the iterate, the interpolation) runs
+// once per (body, component) on the owner threads tid < 3N.  For the
+// evaluation thread t takes the i-slot t % N and the j-part t / N of the
+// j-range; the j-part sums and the pair-rate maxima meet in LDS and are added
+// in a fixed order, so every thread forms the same step and the results do
+// not depend on timing.  (The initialisation passes, run once, use 512
+// threads and 64 or 128 slots.)
 //
 // Per step: prediction with dt = H_-, a pair-rate pass at the predicted
 // positions for H_+ there and the prediction redone for dt = (H_- + H_+)/2;
