@@ -286,6 +286,20 @@ def test_variable_step_errors():
     assert ei.value.status == -5
     d = co.host()
     assert np.array_equal(d["x"], np.zeros((3, 2))) and np.array_equal(d["v"], np.ones((3, 2))) and d["t"] == 0.0
+    # a criterion that fails only at the predicted end point (H_- is finite;
+    # the prediction for dt = H_- overflows the squared separation, so the
+    # rate there is 0 and H_+ is not finite): the step fails with the state
+    # left as it was, for one correction and for several
+    for n_iter in (1, 2, 3):
+        fast = h.state(np.ones(2), np.array([[-0.5, 0.5], [0.0, 0.0], [0.0, 0.0]]),
+                       np.array([[-1e300, 1e300], [0.0, 0.0], [0.0, 0.0]]))
+        h.init(fast)
+        d0 = fast.host()
+        with pytest.raises(HermiteError) as ei:
+            h.step_symmetric(fast, 0.1, n_iter)
+        assert ei.value.status == -5, n_iter
+        d = fast.host()
+        assert np.array_equal(d["x"], d0["x"]) and np.array_equal(d["v"], d0["v"]) and d["t"] == 0.0, n_iter
     # the context still works afterwards
     dt = h.step_symmetric(st, 0.1, 2)
     assert dt > 0.0
