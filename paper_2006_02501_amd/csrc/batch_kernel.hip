@@ -134,10 +134,13 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
     // would exceed 256 registers with them
     constexpr bool kTwo = W == 1 && !(P == 3 && !MIXED && COMP);
     constexpr bool kEndInLoop = W >= 2;
+    constexpr bool kLdsPass = W >= 2;   // segment sums pass through LDS (see the sweep)
     __shared__ double sp[NV][kLanes];      // path of the current iterate: [3 k + c][slot]
     __shared__ T sgm[kLanes];              // G m of every slot
-    // each wave's sums over its sweep steps (a lone wave keeps them in registers)
-    __shared__ double part[W == 1 ? 1 : W][W == 1 ? 1 : NV][W == 1 ? 1 : kLanes];
+    // each wave's sums over its sweep steps (a lone wave keeps them in
+    // registers); during a segment sweep a wave's array carries the j-side
+    // sums from lane to lane
+    __shared__ __align__(16) double part[W == 1 ? 1 : W][W == 1 ? 1 : NV][W == 1 ? 1 : kLanes];
     __shared__ int next_bin;
     const int tid = threadIdx.x;
     // the wave index and every per-bin count below are the same in all lanes
@@ -312,11 +315,98 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                     const T q3 = act ? rinv * rinv2 : T(0);
                     chain_pair<K, T>(r, vv, aa, jj, sgm[jc] * q3, -gm_own * q3, rinv2, acc, tj);
                 };
+                // The same pair in two parts, for the FP64 segment sweep: the
+                // partner's path and G m are read first (into registers), the
+                // chain runs later.  The mixed kernels keep the fused form
+                // above, which stays within 168 registers (three waves per
+                // SIMD).
+                struct JPath {
+                    double p[K + 1][3];
+                    T gm;
+                    bool act;
+                };
+                auto load_j = [&](int jc, bool act, JPath &jp) {
+                    jc = act ? jc : l;
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) jp.p[k][c] = sp[3 * k + c][jc];
+                    jp.gm = sgm[jc];
+                    jp.act = act;
+                };
+                auto pair_with = [&](const JPath &jp, T(&tj)[K + 1][3]) {
+                    T r[3], vv[3], aa[3], jj[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = (T)(jp.p[0][c] - xi[0][c]);
+                        vv[c] = (T)(jp.p[1][c] - xi[1][c]);
+                        aa[c] = K >= 2 ? (T)(jp.p[K >= 2 ? 2 : 0][c] - xi[K >= 2 ? 2 : 0][c]) : T(0);
+                        jj[c] = K >= 3 ? (T)(jp.p[K >= 3 ? 3 : 0][c] - xi[K >= 3 ? 3 : 0][c]) : T(0);
+                    }
+                    T w2 = fma_t(r[0], r[0], fma_t(r[1], r[1], fma_t(r[2], r[2], (T)eps2)));
+                    w2 = jp.act ? w2 : T(1);
+                    const T rinv = rsqrt_t(w2);
+                    const T rinv2 = rinv * rinv;
+                    const T q3 = jp.act ? rinv * rinv2 : T(0);
+                    chain_pair<K, T>(r, vv, aa, jj, jp.gm * q3, -gm_own * q3, rinv2, acc, tj);
+                };
                 T accj[K + 1][3];
 #pragma unroll
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) accj[k][c] = T(0);
+                // A segment sweep of several waves passes the j-side sums
+                // through the wave's own part array, which nothing else uses
+                // between the barrier above and the sums written after the
+                // sweep: every lane writes its sums and reads its successor's,
+                // two doubles or four floats per access.  The LDS carries out
+                // one wave's accesses in order, so the reads see the writes
+                // without a workgroup barrier (the wave barriers only keep the
+                // compiler from moving them).  The values are those of a
+                // lane-to-lane permute, but the LDS unit takes these wide
+                // accesses faster than one permute per 32-bit word.
+                const int sl = succ >> 2;
+                auto lds_pass = [&]() {
+                    T *f = &accj[0][0];
+                    double *base = &part[W == 1 ? 0 : w][0][0];
+                    if constexpr (MIXED) {
+                        constexpr int NG = (NV + 3) / 4;   // fits: NG * 4 floats <= NV doubles
+                        float4 *jb = reinterpret_cast<float4 *>(base);
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            float4 v;
+                            v.x = f[4 * g];
+                            v.y = 4 * g + 1 < NV ? f[4 * g + 1] : 0.0f;
+                            v.z = 4 * g + 2 < NV ? f[4 * g + 2] : 0.0f;
+                            v.w = 4 * g + 3 < NV ? f[4 * g + 3] : 0.0f;
+                            jb[g * kLanes + l] = v;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            const float4 v = jb[g * kLanes + sl];
+                            f[4 * g] = v.x;
+                            if (4 * g + 1 < NV) f[4 * g + 1] = v.y;
+                            if (4 * g + 2 < NV) f[4 * g + 2] = v.z;
+                            if (4 * g + 3 < NV) f[4 * g + 3] = v.w;
+                        }
+                    } else {
+                        constexpr int NP = NV / 2;
+                        double2 *jb = reinterpret_cast<double2 *>(base);
+#pragma unroll
+                        for (int g = 0; g < NP; ++g) jb[g * kLanes + l] = make_double2(f[2 * g], f[2 * g + 1]);
+                        if constexpr ((NV & 1) != 0) base[(NV - 1) * kLanes + l] = f[NV - 1];
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int g = 0; g < NP; ++g) {
+                            const double2 v = jb[g * kLanes + sl];
+                            f[2 * g] = v.x;
+                            f[2 * g + 1] = v.y;
+                        }
+                        if constexpr ((NV & 1) != 0) f[NV - 1] = base[(NV - 1) * kLanes + sl];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                };
                 // the sweep, RING a compile-time tag (one loop per kind)
                 auto sweep = [&](auto ring_tag) {
                     constexpr bool RING = decltype(ring_tag)::value;
@@ -335,6 +425,10 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                         pair(jc, act, accj);
                     };
                     auto pass_on = [&]() {
+                        if constexpr (!RING && kLdsPass) {
+                            lds_pass();
+                            return;
+                        }
 #pragma unroll
                         for (int k = 0; k <= K; ++k)
 #pragma unroll
@@ -355,8 +449,21 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                             }
                         }
                         for (; t <= t1; ++t) {
-                            pass_on();
-                            step_t(t);
+                            if constexpr (!RING && kLdsPass && !MIXED) {
+                                // the partner's path is read before the pass,
+                                // so that these reads do not queue behind it
+                                // (FP64; the mixed kernel has no registers to
+                                // spare for it at three waves per SIMD)
+                                int q2 = q + t;
+                                q2 = q2 >= sz ? q2 - sz : q2;
+                                JPath jp;
+                                load_j(li.lo + q2, t <= half && !(2 * t == sz && q >= half), jp);
+                                pass_on();
+                                pair_with(jp, accj);
+                            } else {
+                                pass_on();
+                                step_t(t);
+                            }
                         }
                     }
                 };
