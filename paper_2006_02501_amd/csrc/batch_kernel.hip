@@ -110,6 +110,16 @@ __global__ __launch_bounds__(kLanes) void batch_init_kernel(BatchPlan pl, int64_
 
 __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
 
+// Orders a wave's LDS accesses for the compiler: none is moved across it,
+// whatever types they use (the segment sweep reads and writes the part array
+// as float4 or double2 and elsewhere as double).  The hardware carries out one
+// wave's LDS accesses in order, so this emits no instruction.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 __device__ constexpr double kInvB[9] = {0.0, 1.0, 1.0 / 2.0, 1.0 / 3.0, 1.0 / 4.0, 1.0 / 5.0, 1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0};
 
 // The row CX[corrector][P][0..P+1] of the position corrector in use (a kernel
@@ -361,7 +371,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 // sweep: every lane writes its sums and reads its successor's,
                 // two doubles or four floats per access.  The LDS carries out
                 // one wave's accesses in order, so the reads see the writes
-                // without a workgroup barrier (the wave barriers only keep the
+                // without a workgroup barrier (wave_lds_order only keeps the
                 // compiler from moving them).  The values are those of a
                 // lane-to-lane permute, but the LDS unit takes these wide
                 // accesses faster than one permute per 32-bit word.
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                             v.w = 4 * g + 3 < NV ? f[4 * g + 3] : 0.0f;
                             jb[g * kLanes + l] = v;
                         }
-                        __builtin_amdgcn_wave_barrier();
+                        wave_lds_order();
 #pragma unroll
                         for (int g = 0; g < NG; ++g) {
                             const float4 v = jb[g * kLanes + sl];
@@ -396,7 +406,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
 #pragma unroll
                         for (int g = 0; g < NP; ++g) jb[g * kLanes + l] = make_double2(f[2 * g], f[2 * g + 1]);
                         if constexpr ((NV & 1) != 0) base[(NV - 1) * kLanes + l] = f[NV - 1];
-                        __builtin_amdgcn_wave_barrier();
+                        wave_lds_order();
 #pragma unroll
                         for (int g = 0; g < NP; ++g) {
                             const double2 v = jb[g * kLanes + sl];
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                         }
                         if constexpr ((NV & 1) != 0) f[NV - 1] = base[(NV - 1) * kLanes + sl];
                     }
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_order();
                 };
                 // the sweep, RING a compile-time tag (one loop per kind)
                 auto sweep = [&](auto ring_tag) {
