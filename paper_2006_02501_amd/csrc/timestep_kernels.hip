@@ -69,17 +69,32 @@ __global__ __launch_bounds__(kQBlock) void qmax_kernel(int64_t n, const double *
     const int64_t j0 = max((int64_t)blockIdx.y * j_chunk, ib0 + 1);
     const int64_t j1 = min((int64_t)blockIdx.y * j_chunk + j_chunk, n);
     double best = 0.0;
-#pragma unroll 4
-    for (int64_t j = j0; j < j1; ++j) {
-        // every load of j is unconditional (a uniform scalar load); the pairs
-        // with j <= i (taken from their other end, or the self pair, whose
-        // rate may be inf or NaN without softening) are left out by a select
+    // the rate of pair (i, j); a larger finite rate replaces best (a NaN rate
+    // compares false and is dropped, as qcombine drops it)
+    auto rate = [&](int64_t j) {
         const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
         const double mj = mass[j];
         const double w = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         const double y = rsqrt64(w);
-        const double q = (G * (mj + mi)) * (y * y * y);
-        best = j > i ? qcombine(q, best) : best;
+        return (G * (mj + mi)) * (y * y * y);
+    };
+    if (j0 >= ib0 + kQBlock) {
+        // every j of the range lies above every i of the workgroup
+#pragma unroll 4
+        for (int64_t j = j0; j < j1; ++j) {
+            const double q = rate(j);
+            best = q > best ? q : best;
+        }
+    } else {
+        // the range meets the workgroup's own i: the pairs with j <= i (taken
+        // from their other end, or the self pair, whose rate may be inf or
+        // NaN without softening) are left out by the select; every load of j
+        // is unconditional (a uniform scalar load)
+#pragma unroll 4
+        for (int64_t j = j0; j < j1; ++j) {
+            const double q = rate(j);
+            best = (j > i && q > best) ? q : best;
+        }
     }
     best = block_qmax(live ? best : 0.0);
     if (threadIdx.x == 0) qpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = best;
