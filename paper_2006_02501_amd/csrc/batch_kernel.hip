@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
     // would exceed 256 registers with them
     constexpr bool kTwo = W == 1 && !(P == 3 && !MIXED && COMP);
     constexpr bool kEndInLoop = W >= 2;
-    constexpr bool kLdsPass = W >= 2;   // segment sums pass through LDS (see the sweep)
+    constexpr bool kLdsPass = W >= 2;   // j-side sums move through LDS (see the sweep)
     __shared__ double sp[NV][kLanes];      // path of the current iterate: [3 k + c][slot]
     __shared__ T sgm[kLanes];              // G m of every slot
     // each wave's sums over its sweep steps (a lone wave keeps them in
@@ -365,18 +365,21 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 for (int k = 0; k <= K; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) accj[k][c] = T(0);
-                // A segment sweep of several waves passes the j-side sums
+                // With several waves the j-side sums move between lanes
                 // through the wave's own part array, which nothing else uses
-                // between the barrier above and the sums written after the
-                // sweep: every lane writes its sums and reads its successor's,
-                // two doubles or four floats per access.  The LDS carries out
-                // one wave's accesses in order, so the reads see the writes
-                // without a workgroup barrier (wave_lds_order only keeps the
-                // compiler from moving them).  The values are those of a
-                // lane-to-lane permute, but the LDS unit takes these wide
-                // accesses faster than one permute per 32-bit word.
+                // between the barrier above and the totals written after the
+                // sweep: every lane writes its sums at slot put and reads
+                // those at slot get, two doubles or four floats per access
+                // (a segment sweep's steps: put l, get the successor; the end
+                // of every sweep: put the slot the sums belong to, get l).
+                // The LDS carries out one wave's accesses in order, so the
+                // reads see the writes without a workgroup barrier
+                // (wave_lds_order only keeps the compiler from moving them).
+                // The values are those of a lane-to-lane permute, but the LDS
+                // unit takes these wide accesses faster than one permute per
+                // 32-bit word.
                 const int sl = succ >> 2;
-                auto lds_pass = [&]() {
+                auto lds_pass = [&](int put, int get) {
                     T *f = &accj[0][0];
                     double *base = &part[W == 1 ? 0 : w][0][0];
                     if constexpr (MIXED) {
@@ -389,12 +392,12 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                             v.y = 4 * g + 1 < NV ? f[4 * g + 1] : 0.0f;
                             v.z = 4 * g + 2 < NV ? f[4 * g + 2] : 0.0f;
                             v.w = 4 * g + 3 < NV ? f[4 * g + 3] : 0.0f;
-                            jb[g * kLanes + l] = v;
+                            jb[g * kLanes + put] = v;
                         }
                         wave_lds_order();
 #pragma unroll
                         for (int g = 0; g < NG; ++g) {
-                            const float4 v = jb[g * kLanes + sl];
+                            const float4 v = jb[g * kLanes + get];
                             f[4 * g] = v.x;
                             if (4 * g + 1 < NV) f[4 * g + 1] = v.y;
                             if (4 * g + 2 < NV) f[4 * g + 2] = v.z;
@@ -404,16 +407,16 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                         constexpr int NP = NV / 2;
                         double2 *jb = reinterpret_cast<double2 *>(base);
 #pragma unroll
-                        for (int g = 0; g < NP; ++g) jb[g * kLanes + l] = make_double2(f[2 * g], f[2 * g + 1]);
-                        if constexpr ((NV & 1) != 0) base[(NV - 1) * kLanes + l] = f[NV - 1];
+                        for (int g = 0; g < NP; ++g) jb[g * kLanes + put] = make_double2(f[2 * g], f[2 * g + 1]);
+                        if constexpr ((NV & 1) != 0) base[(NV - 1) * kLanes + put] = f[NV - 1];
                         wave_lds_order();
 #pragma unroll
                         for (int g = 0; g < NP; ++g) {
-                            const double2 v = jb[g * kLanes + sl];
+                            const double2 v = jb[g * kLanes + get];
                             f[2 * g] = v.x;
                             f[2 * g + 1] = v.y;
                         }
-                        if constexpr ((NV & 1) != 0) f[NV - 1] = base[(NV - 1) * kLanes + sl];
+                        if constexpr ((NV & 1) != 0) f[NV - 1] = base[(NV - 1) * kLanes + get];
                     }
                     wave_lds_order();
                 };
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                     };
                     auto pass_on = [&]() {
                         if constexpr (!RING && kLdsPass) {
-                            lds_pass();
+                            lds_pass(l, sl);
                             return;
                         }
 #pragma unroll
@@ -481,22 +484,28 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 else sweep(std::false_type{});
                 // lane l now holds the j-side sums of slot h: l + t1 (ring)
                 // or local body q + t1 (segments); a wave without steps
-                // holds zeros
-                // Each lane takes the j-side sums of its own slot from the
-                // lane holding them, l - t1 (ring) or local body q - t1
-                // (segments), and adds them to its i-side sums.  A lone wave
-                // keeps the result in registers; several waves put theirs in
-                // LDS for the component owners.
-                const int src = ring ? ((l - t1) & (kLanes - 1)) : li.lo + ((q - t1 % sz) % sz + sz) % sz;
+                // holds zeros.  Every slot's j-side sums go to that slot's
+                // lane and are added to its i-side sums:
+                //  - several waves: through the wave's part array (each lane
+                //    puts its sums at slot h and takes those of slot l), and
+                //    the totals go to part for the component owners;
+                //  - a lone wave: each lane takes them from the lane holding
+                //    them, l - t1 (ring) or local body q - t1 (segments), by
+                //    ds_bpermute, and keeps the totals in registers.
                 double own[W == 1 ? K + 1 : 1][3];
+                if constexpr (kLdsPass) {
+                    lds_pass(ring ? ((l + t1) & (kLanes - 1)) : li.lo + (q + t1 % sz) % sz, l);
 #pragma unroll
-                for (int k = 0; k <= K; ++k)
+                    for (int k = 0; k <= K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double s = (double)acc[k][c] + (double)lane_from(4 * src, accj[k][c]);
-                        if constexpr (W == 1) own[k][c] = s;
-                        else part[w][3 * k + c][l] = s;
-                    }
+                        for (int c = 0; c < 3; ++c) part[w][3 * k + c][l] = (double)acc[k][c] + (double)accj[k][c];
+                } else {
+                    const int src = ring ? ((l - t1) & (kLanes - 1)) : li.lo + ((q - t1 % sz) % sz + sz) % sz;
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) own[k][c] = (double)acc[k][c] + (double)lane_from(4 * src, accj[k][c]);
+                }
                 __syncthreads();   // every wave's sums are in part; sp may change
                 // a system past its own iteration count keeps its last iterate
                 if (it >= my_iter) continue;
