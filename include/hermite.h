@@ -268,13 +268,15 @@ hermite_status hermite_batch_run_iters(hermite_ctx *ctx, hermite_state *s, const
  *   ring_min    bins whose largest system has at least ring_min bodies sweep
  *               the whole wave as one ring, the j-side sums of a pair moving
  *               between lanes by DPP; the others sweep each system as a ring
- *               of its own, the sums moving by permutes (2..65; 65: never)
+ *               of its own, the sums moving by lane permutes (through LDS with
+ *               two or more waves) (2..65; 65: never)
  * Results are bitwise the same for every workgroup count (each bin is
  * computed by one workgroup in a fixed order); waves and ring_min change the
  * order of the sums, hence the rounding.  E_ARG for values outside these
  * sets or a context that is not batched.  hermite_batch_get_launch reports
  * the shape in use (the creation default: 2 waves, 1 when no system has
- * more than 16 bodies; ring_min 57; every resident workgroup).
+ * more than 16 bodies, 4 when every bin fits on the GPU at once with 4 waves
+ * each; ring_min 57; every resident workgroup).
  *
  * hermite_batch_autotune times every supported shape (waves 1, 2, 4;
  * ring_min 57 or none; from half to all of the resident workgroups) for

@@ -403,14 +403,17 @@ int batch_resident(const hermite_ctx *ctx, const hermite::BatchShape &sh)
     return std::max(1, per_cu) * ctx->cus;
 }
 
-// Default batched shape: two waves per bin for the FP64 chain, four for the
-// mixed one (whose smaller registers let three waves share a SIMD), the
-// whole-wave ring from 57 bodies, and as many persistent workgroups as the
-// GPU holds: the fastest shapes on the 4096-system workload.  Systems of at
-// most 16 bodies take at most 8 sweep steps, too few to share: one wave.
+// Default batched shape: two waves per bin, the whole-wave ring from 57
+// bodies, and as many persistent workgroups as the GPU holds (the fastest
+// shape on the 4096-system workload, in both chains).  Systems of at most 16
+// bodies take at most 8 sweep steps, too few to share: one wave.  A batch
+// whose bins all fit on the GPU at once with four waves each takes four: a
+// bin's time then sets the run's, and four waves split its sweep further
+// (one 64-body system, 4th order: 4.0 against 7.4 us per step).
 hermite::BatchShape default_batch_shape(const hermite_ctx *ctx)
 {
-    const int waves = ctx->max_size <= 16 ? 1 : 2;
+    int waves = ctx->max_size <= 16 ? 1 : 2;
+    if (waves == 2 && ctx->n_bins <= batch_resident(ctx, hermite::BatchShape{0, 4, 57})) waves = 4;
     hermite::BatchShape sh{0, waves, 57};
     sh.workgroups = batch_resident(ctx, sh);
     return sh;
