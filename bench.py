@@ -801,6 +801,10 @@ def main():
                     help="also run the Sec. 3.3 N-body test grid (Table 1) to t = 100 pi (a few minutes)")
     ap.add_argument("--table1-only", action="store_true", help="run only the Table 1 grid")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
+    ap.add_argument("--other-configs-only", action="store_true",
+                    help="run only the 131k cluster and the 1M-body disc")
+    ap.add_argument("--small-systems-only", action="store_true",
+                    help="run only the 64-body ring and the Kepler orbit")
     ap.add_argument("--table1-etas", default="0.08,0.04,0.02,0.01,0.005")
     ap.add_argument("--table1-iters", default="3,4", help="iteration counts of the 8th-order rows")
     ap.add_argument("--table1-realizations", type=int, default=1,
@@ -831,6 +835,12 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": batched(args.batched_steps, per_system=not args.no_per_system,
                                              autotune=not args.no_autotune)}), flush=True)
+        return
+    if args.other_configs_only:
+        print(json.dumps({"other_configs": other_configs()}), flush=True)
+        return
+    if args.small_systems_only:
+        print(json.dumps({"small_systems": small_systems()}), flush=True)
         return
 
     calib = calibrate_copy() if args.calibrate_copy else None
