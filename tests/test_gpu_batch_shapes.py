@@ -282,3 +282,21 @@ def test_graph_recaptured_on_shape_change(batch_workload):
     da, db = a.host(), b.host()
     assert np.array_equal(da["x"], db["x"]) and np.array_equal(da["v"], db["v"])
     bh.close()
+
+
+def test_default_shape_follows_the_batch(batch_workload):
+    # one wave when no system has more than 16 bodies; four when every bin
+    # fits on the GPU at once with four waves (a few bins); two for the full
+    # workload (2156 bins, more than the GPU holds at four waves each)
+    cases = [([64], 4), ([64, 58, 6, 33, 31], 4), ([2, 2, 2], 1), ([16, 16, 9], 1)]
+    for sizes, waves in cases:
+        e = _edge_set(batch_workload, sizes)
+        for precision in ("fp64", "mixed"):
+            bh = BatchHermite(8, e["offsets"], precision=precision, device=DEV)
+            wg, w, rm = bh.get_launch()
+            assert (w, rm) == (waves, 57), (sizes, precision, wg, w, rm)
+            assert 1 <= wg <= len(sizes)
+            bh.close()
+    bh = BatchHermite(8, batch_workload["offsets"], device=DEV)
+    assert bh.get_launch()[1:] == (2, 57)
+    bh.close()
