@@ -380,6 +380,7 @@ __global__ __launch_bounds__(kLanes * W, 2) void batch_run_kernel(
                 // 32-bit word.
                 const int sl = succ >> 2;
                 auto lds_pass = [&](int put, int get) {
+                    if constexpr (!kLdsPass) return;   // a lone wave has no part array to pass through
                     T *f = &accj[0][0];
                     double *base = &part[W == 1 ? 0 : w][0][0];
                     if constexpr (MIXED) {
