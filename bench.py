@@ -532,12 +532,14 @@ def small_systems():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         d = st.host()
+        wg, waves, ring_min = bh.get_launch()
         bh.close()
         E0 = _system_energies(w["mass"], w["x"], w["v"], off)[0]
         E1 = _system_energies(d["mass"], d["x"], d["v"], off)[0]
         inter = steps * w["n_iter"] * n * (n - 1)
         res = {"bodies": n, "order": 4, "n_iter": w["n_iter"], "dt": w["dt"], "steps": steps,
                "batched_one_system_ms": ms, "us_per_step": ms * 1e3 / steps,
+               "launch": {"workgroups": wg, "waves_per_bin": waves, "ring_min": ring_min},
                "interactions_per_s": inter / (ms / 1e3), "energy_rel_change": E1 / E0 - 1.0}
         if n == 2:
             ea, wa = _ecc_omega(w["mass"], w["x"], w["v"])
